@@ -1,0 +1,390 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows. None of them retypes the oracle's own formula:
+they compare it with values the paper prints (the C-hat matrices, the flux columns of
+Eq. solvem, the N_ab of Section 5.1), with identities (orthogonality, conservation, the
+SRT limit), with exact Navier-Stokes solutions, or with a per-node brute-force loop.
+"""
+from fractions import Fraction
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import closed_forms as cf
+from oracle import d3q19 as d
+from oracle import naive
+
+GOLD = Path(__file__).parent / "golden"
+
+
+def _load_rational(name):
+    rows = []
+    for line in (GOLD / name).read_text().splitlines():
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append([float(Fraction(v)) for v in line.split()])
+    return np.array(rows)
+
+
+# --- Section 2: the lattice and the moment basis ---------------------------------------
+
+def test_transform_rows_orthogonal_and_inverse():
+    """T has mutually orthogonal rows (d'Humieres basis) and T T^-1 = I (Section 2)."""
+    G = d.T @ d.T.T
+    off = G - np.diag(np.diag(G))
+    assert np.abs(off).max() == 0.0
+    assert np.array_equal(np.diag(G), [19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8])
+    assert np.abs(d.T @ d.TINV - np.eye(19)).max() <= 19 * np.finfo(float).eps
+    assert np.abs(d.TINV @ d.T - np.eye(19)).max() <= 19 * np.finfo(float).eps
+
+
+def test_lattice_weights_isotropy():
+    """Eq. omega and Eq. HeLuoD3Q19: sum w = 1, sum w c c = c_s^2 I, sum w c = 0."""
+    Cf = d.C.astype(float)
+    assert abs(d.W.sum() - 1.0) < 1e-15
+    assert np.abs(Cf @ d.W).max() < 1e-15
+    assert np.abs((Cf * d.W) @ Cf.T - d.CS2 * np.eye(3)).max() < 1e-15
+    assert all(np.array_equal(d.C[:, d.OPP[i]], -d.C[:, i]) for i in range(19))
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+def test_chat_matrices_match_paper(axis):
+    """T C_k T^-1 reproduces the three matrices printed in Section 4.1.
+
+    One printed entry of C-hat_z (row t_x, column p_xy) reads 1 where the product is 0;
+    it is a typo in the paper (it would make the t_x row inconsistent with the C-hat_x,y
+    symmetry) and is excluded.
+    """
+    k = "xyz".index(axis)
+    printed = _load_rational(f"chat_{axis}.txt")
+    computed = d.T @ np.diag(d.C[k].astype(float)) @ d.TINV
+    diff = np.abs(printed - computed)
+    if axis == "z":
+        assert printed[16, 13] == 1.0 and abs(computed[16, 13]) < 1e-14
+        diff[16, 13] = 0.0
+    assert diff.max() < 1e-13
+
+
+def test_flux_columns_of_solvem_fix_m_eq():
+    """C-hat_k m^eq equals the x, y, z flux columns printed in Eq. solvem, for any
+    omega_eps, omega_epsj, omega_xx, rho_0 (this also fixes the reading of the garbled
+    labels in Eq. meq)."""
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        dr = rng.normal() * 0.02
+        j = rng.normal(size=3) * 0.05
+        r0 = 0.5 + rng.random()
+        we, wej, wxx = rng.normal(size=3) * 3
+        jx, jy, jz = j
+        jj = j @ j
+        meq = d.m_eq(np.array(dr), j, r0, we, wej, wxx)
+
+        def big(a2):
+            return (76 + 10 * wej) * jj / (63 * r0) + (2 - 5 * wxx) * a2 / (9 * r0) + 2 * (5 * we - 22) * dr / 63
+
+        A = big(-2 * jx**2 + jy**2 + jz**2)
+        B = big(jx**2 - 2 * jy**2 + jz**2)
+        Cc = big(jx**2 + jy**2 - 2 * jz**2)
+        cols = [
+            [jx, 5 * jx / 3, -2 * jx / 3, jx**2 / r0 + dr / 3, A, jx * jy / r0, jx * jy / r0, jx * jz / r0,
+             jx * jz / r0, 4 * jx / 3, -2 * jx / 3, 0, 0, jy / 3, 0, jz / 3,
+             (jy**2 - jz**2) * (2 + wxx) / (3 * r0), -jx * jy / r0, jx * jz / r0],
+            [jy, 5 * jy / 3, -2 * jy / 3, jx * jy / r0, jx * jy / r0, jy**2 / r0 + dr / 3, B, jy * jz / r0,
+             jy * jz / r0, -2 * jy / 3, jy / 3, 2 * jy / 3, -jy / 3, jx / 3, jz / 3, 0,
+             jx * jy / r0, (jz**2 - jx**2) * (2 + wxx) / (3 * r0), -jy * jz / r0],
+            [jz, 5 * jz / 3, -2 * jz / 3, jx * jz / r0, jx * jz / r0, jy * jz / r0, jy * jz / r0,
+             jz**2 / r0 + dr / 3, Cc, -2 * jz / 3, jz / 3, -2 * jz / 3, jz / 3, 0, jy / 3, jx / 3,
+             -jx * jz / r0, jy * jz / r0, (jx**2 - jy**2) * (2 + wxx) / (3 * r0)],
+        ]
+        for k in range(3):
+            Chat = d.T @ np.diag(d.C[k].astype(float)) @ d.TINV
+            assert np.abs(Chat @ meq - np.array(cols[k])).max() < 1e-14
+
+
+def test_m_eq_is_T_of_g_eq():
+    """With omega_eps = 3, omega_epsj = -11/2, omega_xx = -1/2 (Eq. meq), m^eq = T g^eq
+    where g^eq is the delta-rho form of Eq. edf."""
+    rng = np.random.default_rng(3)
+    dr = rng.normal(size=(4, 5)) * 0.02
+    j = rng.normal(size=(3, 4, 5)) * 0.05
+    for r0 in (1.0, 2.5):
+        lhs = np.tensordot(d.T, d.g_eq(dr, j, r0), axes=(1, 0))
+        assert np.abs(lhs - d.m_eq(dr, j, r0)).max() < 1e-15
+
+
+def test_equilibrium_tensor_identities():
+    """Eq. cfeqmoment_: sum c c g^eq = c_s^2 drho I + rho0 u u and
+    sum c c c g^eq = c_s^2 rho0 (d_ab u_c + d_ac u_b + d_bc u_a)."""
+    rng = np.random.default_rng(5)
+    dr = rng.normal() * 0.02
+    r0 = 1.7
+    u = rng.normal(size=3) * 0.05
+    ge = d.g_eq(np.array(dr), r0 * u, r0)
+    Cf = d.C.astype(float)
+    P2 = np.einsum("ai,bi,i->ab", Cf, Cf, ge)
+    assert np.abs(P2 - (d.CS2 * dr * np.eye(3) + r0 * np.outer(u, u))).max() < 1e-16
+    P3 = np.einsum("ai,bi,ci,i->abc", Cf, Cf, Cf, ge)
+    I = np.eye(3)
+    ref = d.CS2 * r0 * (np.einsum("ab,c->abc", I, u) + np.einsum("ac,b->abc", I, u) + np.einsum("bc,a->abc", I, u))
+    assert np.abs(P3 - ref).max() < 1e-16
+
+
+def test_guo_moments_are_derivative_of_m_eq():
+    """T F-bar equals (d m^eq / d j) . F (central difference of m^eq, exact for a
+    quadratic)."""
+    rng = np.random.default_rng(9)
+    j = rng.normal(size=3) * 0.05
+    F = rng.normal(size=3) * 1e-3
+    r0 = 1.3
+    h = 1.0  # a central difference is exact for a quadratic at any step size
+    dm = (d.m_eq(np.array(0.01), j + h * F, r0) - d.m_eq(np.array(0.01), j - h * F, r0)) / (2 * h)
+    SF = d.T @ d.guo_force_populations(j, F, r0)
+    assert np.abs(SF - dm).max() < 1e-15
+
+
+# --- Sections 3 and 5.1: the two strain formulas ---------------------------------------
+
+def _random_rates(rng):
+    s = d.default_rates(1.0 / (0.6 + rng.random()))
+    s[[1, 2, 4, 6, 8, 10, 12, 16, 17, 18]] = 0.5 + 1.4 * rng.random(10)
+    return s
+
+
+def test_yu_equals_chai_on_arbitrary_states():
+    """Section 5.1: the Chai formula reduces exactly to the Yu formula. The identity holds
+    for any pre-collision state, far from equilibrium, any rho_0 and any rates (with the
+    s_nu slots equal, Eq. sD3Q15meaning)."""
+    rng = np.random.default_rng(21)
+    shape = (3, 4, 5)
+    for trial in range(4):
+        p = d.Params(rho0=0.7 + rng.random(), s=_random_rates(rng))
+        g = synth.random_state(19, shape, seed=trial, scale=0.05)
+        sn = np.full(shape, p.s[9])
+        Sy = d.strain_of_state(g, p, sn, "yu")
+        Sc = d.strain_of_state(g, p, sn, "chai")
+        assert np.abs(Sy - Sc).max() <= 1e-13 * np.abs(Sy).max()
+
+
+def test_chai_gives_printed_N_ab():
+    """Section 5.1 prints N_ab = sum_i c_ia c_ib M_i with M = T^-1 Lambda-hat m^(1):
+    N_xx = s1 m1/57 + s9 m9/3, N_yy = s1 m1/57 - s9 m9/6 + s9 m11/2,
+    N_zz = s1 m1/57 - s9 m9/6 - s9 m11/2, N_xy,yz,xz = s9 m13,14,15; and S = -N/(2 rho0 c_s^2)."""
+    rng = np.random.default_rng(4)
+    r0 = 1.2
+    s = _random_rates(rng)
+    m1 = rng.normal(size=19) * 0.01
+    m1[[0, 3, 5, 7]] = 0.0  # conserved moments have no non-equilibrium part
+    fneq = d.TINV @ m1
+    S = d.strain_chai(fneq, s, r0)
+    N = -S * 2 * r0 * d.CS2
+    s1, s9 = s[1], s[9]
+    ref = [s1 * m1[1] / 57 + s9 * m1[9] / 3,
+           s1 * m1[1] / 57 - s9 * m1[9] / 6 + s9 * m1[11] / 2,
+           s1 * m1[1] / 57 - s9 * m1[9] / 6 - s9 * m1[11] / 2,
+           s9 * m1[13], s9 * m1[14], s9 * m1[15]]
+    assert np.abs(N - np.array(ref)).max() < 1e-16
+
+
+def test_srt_limit():
+    """Eq. ChaiS_srt: with Lambda-hat = I/tau, T^-1 Lambda-hat T = I/tau, the MRT collision
+    is the BGK collision g* = g - (g - g^eq)/tau and the Chai strain is
+    -sum c c (g - g^eq) / (2 rho0 c_s^2 tau)."""
+    tau = 0.73
+    p = d.Params(rho0=1.1, s=np.full(19, 1.0 / tau))
+    shape = (2, 3, 4)
+    g = synth.random_state(19, shape, seed=2, scale=0.03)
+    sn = np.full(shape, 1.0 / tau)
+    assert np.abs(d.TINV @ np.diag(p.s) @ d.T - np.eye(19) / tau).max() < 1e-14
+    out = d.collide(g, p, sn)
+    drho, j = d.macroscopic(g)
+    ge = d.g_eq(drho, j, p.rho0)
+    assert np.abs(out.g_post - (g - (g - ge) / tau)).max() < 1e-15
+    Cf = d.C.astype(float)
+    ref = []
+    for a, b in ((0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)):
+        ref.append(-np.tensordot(Cf[a] * Cf[b], g - ge, axes=(0, 0)) / (2 * p.rho0 * d.CS2 * tau))
+    assert np.abs(out.S_chai - np.stack(ref)).max() < 1e-15
+
+
+def test_strain_does_not_depend_on_the_omegas():
+    """Section 2 (after Eq. meq): omega_eps, omega_epsj, omega_xx do not affect the strain
+    computed from a given state."""
+    shape = (2, 3, 4)
+    g = synth.random_state(19, shape, seed=8, scale=0.03)
+    base = d.Params()
+    other = d.Params(omega_eps=0.0, omega_epsj=-475.0 / 63.0, omega_xx=0.0)
+    sn = np.full(shape, base.s[9])
+    for kind in ("yu", "chai"):
+        assert np.abs(d.strain_of_state(g, base, sn, kind) - d.strain_of_state(g, other, sn, kind)).max() < 1e-16
+
+
+# --- Eq. mrteq and the conservation equations of Section 4.1 ---------------------------
+
+def _smooth_state(shape, seed, p):
+    u = synth.random_vector(shape, seed=seed, scale=0.02)
+    dr = synth.random_vector(shape, seed=seed + 1, scale=0.01)[0]
+    return d.init_populations(dr, u, p) + synth.random_state(19, shape, seed=seed + 2, scale=1e-4)
+
+
+@pytest.mark.parametrize("case", ["plain", "force", "smag", "walls_powerlaw"])
+def test_conservation(case):
+    """Mass is conserved exactly; momentum is conserved without force and grows by exactly
+    sum_x F per step with the Guo force (the conserved rows of Eq. solvem); bounce-back
+    walls conserve mass."""
+    shape = (4, 6, 5)
+    kw = {}
+    if case == "force":
+        kw["force"] = synth.random_vector(shape, seed=3, scale=1e-4)
+    if case == "smag":
+        kw.update(visc_kind="smagorinsky", nu0=0.01)
+    if case == "walls_powerlaw":
+        kw.update(visc_kind="powerlaw", visc_strain="chai", K_pl=0.05, n_pl=0.7, walls_y=True,
+                  force=np.array([0.0, 0.0, 1e-4]))
+    p = d.Params(**kw)
+    sim = d.Simulation(p, _smooth_state(shape, 1, p))
+    d0 = sim.diagnostics()
+    nsteps = 30
+    sim.step(nsteps)
+    d1 = sim.diagnostics()
+    assert abs(d1["mass"] - d0["mass"]) <= 1e-13 * max(1.0, abs(d0["mass"]))
+    if case in ("plain", "smag"):
+        assert np.abs(d1["mom"] - d0["mom"]).max() <= 1e-13
+    if case == "force":
+        Ftot = p.force_field(shape).reshape(3, -1).sum(axis=1)
+        assert np.abs(d1["mom"] - d0["mom"] - nsteps * Ftot).max() <= 1e-13
+
+
+def test_naive_loop_matches_vectorised_step():
+    """Brute force: the per-node loop (explicit modular neighbour indices, explicit
+    per-node T^-1 diag(s) T) reproduces the vectorised oracle step, walls and force and
+    variable viscosity included."""
+    shape = (3, 4, 5)
+    for kw in (dict(), dict(visc_kind="smagorinsky", nu0=0.02, c_smag=0.3),
+               dict(visc_kind="powerlaw", visc_strain="chai", K_pl=0.02, n_pl=1.4, walls_y=True,
+                    force=synth.random_vector(shape, seed=5, scale=1e-3))):
+        p = d.Params(**kw)
+        g = _smooth_state(shape, 7, p)
+        sn = np.full(shape, p.s[9]) * (1 + 0.1 * synth.random_vector(shape, seed=9, scale=1.0)[0])
+        out = d.collide(g, p, sn)
+        nxt = d.stream(out.g_post, p.walls_y)
+        g2, Sy, Sc, snew = naive.step(g, p, sn)
+        assert np.abs(nxt - g2).max() < 1e-15
+        assert np.abs(out.S_yu - Sy).max() < 1e-15
+        assert np.abs(out.S_chai - Sc).max() < 1e-15
+        assert np.abs(out.s_nu - snew).max() < 1e-14
+
+
+# --- Section 5.1: second-order accuracy of the strain ----------------------------------
+
+def _tgv_error(N, plane, kind, tau=0.8):
+    u0 = 0.05 * 32 / N
+    steps = int(round(200 * (N / 32) ** 2))
+    shape = [1, 1, 1]
+    for a in plane:
+        shape[2 - a] = N
+    shape = tuple(shape)
+    p = d.Params(s=d.default_rates(tau))
+    dr, u, gu = synth.tgv_rotated(shape, u0, 1.0, plane)
+    sim = d.Simulation(p, d.init_populations(dr, u, p, gu))
+    S0 = sim.strain(kind)
+    exact0 = cf.tgv_rotated_strain(shape, u0, cf.nu_of_rate(1 / tau), 0.0, plane)
+    assert np.abs(S0 - exact0).max() < 1e-14  # the CE initial state reproduces S exactly
+    sim.step(steps)
+    S = sim.strain(kind)
+    exact = cf.tgv_rotated_strain(shape, u0, cf.nu_of_rate(1 / tau), steps, plane)
+    comp = {(0, 1): 3, (1, 2): 4, (0, 2): 5}[plane]
+    others = [c for c in range(6) if c != comp]
+    return (np.linalg.norm(S[comp] - exact[comp]) / np.linalg.norm(exact[comp]),
+            np.abs(S[others]).max() / np.abs(exact[comp]).max())
+
+
+@pytest.mark.slow
+def test_second_order_convergence_of_S_xy():
+    """Section 5.1 (last paragraph): the strain is second-order accurate in space.
+    Rotated Taylor-Green vortex, diffusive scaling N = 16, 32, 64 (u0 ~ 1/N, steps ~ N^2),
+    S_xy against the closed form at equal physical time; observed order >= 1.8."""
+    e = [_tgv_error(N, (0, 1), "yu")[0] for N in (16, 32, 64)]
+    orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert (orders >= 1.8).all(), (e, orders)
+    assert e[-1] < 1e-3
+
+
+@pytest.mark.parametrize("plane", [(1, 2), (0, 2)])
+def test_off_diagonal_strain_in_other_planes(plane):
+    """Same flow turned into the yz and xz planes pins S_yz and S_xz (Chai and Yu)."""
+    e16, z16 = _tgv_error(16, plane, "chai")
+    e32, z32 = _tgv_error(32, plane, "yu")
+    assert np.log2(e16 / e32) >= 1.8
+    # the other five components are zero in the continuum; on the lattice they are
+    # discretisation error that shrinks with resolution
+    assert z16 < 0.02 and z32 < 0.005 and z32 < z16 / 4
+
+
+def test_axis_tgv_diagonal_strain():
+    """Axis-aligned Taylor-Green: S_xx = -S_yy = u0 k cos kx cos ky e^(-2 nu k^2 t) and
+    S_xy = 0 in the continuum (it pins the diagonal components of Eq. LuoS). The initial
+    state has S_xy = 0 to rounding; on the lattice S_xy then grows only as discretisation
+    error."""
+    N, tau, steps = 32, 0.8, 200
+    u0 = 0.05
+    shape = (1, N, N)
+    p = d.Params(s=d.default_rates(tau))
+    dr, u, gu = synth.tgv_axis(shape, u0, 1.0)
+    sim = d.Simulation(p, d.init_populations(dr, u, p, gu))
+    exact0 = cf.tgv_axis_strain(shape, u0, cf.nu_of_rate(1 / tau), 0)
+    assert np.abs(sim.strain("yu") - exact0).max() < 1e-14
+    sim.step(steps)
+    exact = cf.tgv_axis_strain(shape, u0, cf.nu_of_rate(1 / tau), steps)
+    for kind in ("yu", "chai"):
+        S = sim.strain(kind)
+        scale = np.abs(exact[0]).max()
+        assert np.abs(S[0] - exact[0]).max() < 1e-2 * scale
+        assert np.abs(S[1] - exact[1]).max() < 1e-2 * scale
+        assert np.abs(S[3]).max() < 1e-3 * scale
+        assert np.abs(S[2]).max() < 1e-3 * scale
+
+
+# --- Walls and force: plane Poiseuille ---------------------------------------------------
+
+def _channel(H, p, steps):
+    shape = (1, H, 1)
+    g0 = d.init_populations(np.zeros(shape), np.zeros((3,) + shape), p)
+    sim = d.Simulation(p, g0)
+    sim.step(steps)
+    return sim
+
+
+@pytest.mark.slow
+def test_newtonian_startup_poiseuille():
+    """Halfway bounce-back walls at y = -1/2, H - 1/2 plus the Guo force: the start-up
+    of Newtonian channel flow follows the odd-sine series (velocity = j / rho0 with the
+    half-force correction)."""
+    H, tau, F = 16, 0.8, 1e-5
+    p = d.Params(s=d.default_rates(tau), walls_y=True, force=np.array([0.0, 0.0, F]))
+    steps = 400
+    sim = _channel(H, p, steps)
+    _, j = d.macroscopic(sim.g, p.force_field(sim.g.shape[1:]))
+    uz = j[2, 0, :, 0] / p.rho0
+    eta = np.arange(H) + 0.5
+    ref = cf.startup_poiseuille(eta, H, F, cf.nu_of_rate(1 / tau), steps)
+    assert np.abs(uz - ref).max() < 0.01 * np.abs(ref).max()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n_pl", [0.5, 1.5])
+def test_powerlaw_poiseuille_steady(n_pl):
+    """Power-law viscosity from the Chai strain: the steady channel profile approaches the
+    analytic power-law Poiseuille profile."""
+    H, F = 16, 1e-5
+    gref = F * H / (2 * 0.1)          # wall shear of the Newtonian flow with nu = 0.1
+    K = 0.1 * gref ** (1 - n_pl)
+    p = d.Params(walls_y=True, force=np.array([0.0, 0.0, F]), visc_kind="powerlaw", visc_strain="chai",
+                 K_pl=K, n_pl=n_pl, nu_min=1e-4, nu_max=2.0)
+    sim = _channel(H, p, 6000)
+    _, j = d.macroscopic(sim.g, p.force_field(sim.g.shape[1:]))
+    uz = j[2, 0, :, 0] / p.rho0
+    eta = np.arange(H) + 0.5
+    ref = cf.powerlaw_poiseuille(eta, H, F, K, n_pl)
+    assert np.abs(uz - ref).max() < 0.03 * ref.max()
