@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D3Q19 MRT collide-stream-strain step on one MI355X.
+
+Workload (the headline configuration): D3Q19 He-Luo MRT LES on a 256^3 periodic box,
+FP32 populations, Smagorinsky eddy viscosity (C_s = 0.1) driven by the Yu strain of every
+node, initial velocity a seeded random solenoidal field with spectrum k^4 exp(-2 (k/4)^2)
+and u_rms = 0.04 (seed 1704). One step = one launch of the fused kernel (pull streaming,
+moments, equilibrium, Yu strain, Smagorinsky s_nu, relaxation, back-transform, store) over
+all 16.8 M nodes; the FP64 diagnostics reduction (mass, momentum, energy, strain, max |u|,
+non-finite watchdog) runs every 100 steps inside the timed region.
+
+Output: one JSON line. ``value`` is MLUPS (million lattice-node updates per second) with
+inputs resident in HBM. ``roofline`` prices the step kernel's algorithmic bytes per node
+(19 reads + 19 writes of 4 B, plus the 4 B read and write of the lagged s_nu field) against
+the 8 TB/s HBM peak, timed with HIP events around every launch on the stream it runs on.
+``extra`` carries the FP16/BF16-stored 384^3 runs and their FP32 reference.
+``cpu_baseline`` times the FP64 oracle on a bounded slab of the same workload.
+
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS & % HBM roofline, D3Q19 MRT+strain, FP32 vs FP16-stored; adjoint/fwd cost"
+KERNEL_SOURCES = ["paper_1704_07559_amd/csrc/kernels_d3q19.hip", "paper_1704_07559_amd/csrc/d3q19.h",
+                  "paper_1704_07559_amd/csrc/internal.h", "paper_1704_07559_amd/csrc/codec.h",
+                  "paper_1704_07559_amd/csrc/static_for.h"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update((ROOT / rel).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name: str, sha: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source (else None)."""
+    f = ROOT / "profiles" / f"traffic_{name}.txt"
+    if not f.exists():
+        return None
+    kv = {}
+    for line in f.read_text().splitlines():
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def rates(tau_nu):
+    # d'Humieres rates with s_nu = 1/tau_nu in slots 9, 11, 13, 14, 15
+    sn = 1.0 / tau_nu
+    return [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sn, 1.4, sn, 1.4, sn, sn, sn, 1.98, 1.98, 1.98]
+
+
+def les_params(capi, n, storage):
+    tau0 = 0.51  # nu0 = 1/300
+    return capi.Params(nx=n, ny=n, nz=n, lattice=capi.LBM_D3Q19, storage=storage, s=rates(tau0),
+                       visc_kind=capi.LBM_VISC_SMAGORINSKY, visc_strain=capi.LBM_STRAIN_YU,
+                       nu0=(tau0 - 0.5) / 3.0, c_smag=0.1)
+
+
+def time_run(sim, steps, warmup, reduce_every=100):
+    """Run warmup + timed steps; returns (wall seconds, mean kernel seconds, last diagnostics)."""
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    diag = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        sim.step(1)
+        ev[k][1].record()
+        if (k + 1) % reduce_every == 0:
+            diag = sim.reduce(allow_nonfinite=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = sum(a.elapsed_time(b) for a, b in ev) / steps / 1e3
+    if diag is None:
+        diag = sim.reduce(allow_nonfinite=True)
+    return wall, kern, diag
+
+
+def cpu_baseline(u_full, n_slab=64, steps=6):
+    """FP64 oracle on a 256 x 256 x n_slab z-slab of the same initial field (periodic in the
+    slab), Smagorinsky from Yu, ``steps`` steps."""
+    import numpy as np
+    from oracle import d3q19 as od
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    u = np.ascontiguousarray(u_full[:, :n_slab])
+    shape = u.shape[1:]
+    tau0 = 0.51
+    p = od.Params(s=od.default_rates(tau0), visc_kind="smagorinsky", visc_strain="yu", nu0=(tau0 - 0.5) / 3.0,
+                  c_smag=0.1)
+    sim = od.Simulation(p, od.init_populations(np.zeros(shape), u, p))
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    nodes = int(np.prod(shape))
+    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle, {shape[2]}x{shape[1]}x{shape[0]} z-slab of the 256^3 workload, "
+                      f"{steps} steps, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="edge of the cubic LES box (default 256)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 384^3 FP16/BF16/FP32 storage runs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(3)
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+        return
+
+    import synth
+    from paper_1704_07559_amd import capi, lbm
+
+    n = args.n
+    log(f"generating the {n}^3 initial field")
+    u = synth.spectrum_velocity((n, n, n), seed=1704, u_rms=0.04)
+    rho_u = lbm.rho_u_field(np.zeros((n, n, n)), u)
+    sim = lbm.LBM(les_params(capi, n, capi.LBM_F32), rho_u)
+    del rho_u
+    N = n ** 3
+    log(f"FP32 {n}^3: {args.warmup} warmup + {args.steps} timed steps")
+    wall, kern, diag = time_run(sim, args.steps, args.warmup)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    mlups = N * args.steps / wall / 1e6
+    bytes_per_node = 19 * 4 * 2 + 4 * 2
+    achieved = bytes_per_node * N / kern / 1e9
+    sha = kernel_source_sha()
+    traffic = read_traffic("step_d3q19_f32_les256", sha)
+    result = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 He-Luo MRT LES {n}^3 periodic, FP32 populations, Smagorinsky C_s=0.1 "
+                               f"from the Yu strain, k^4 exp(-2(k/4)^2) spectrum seed 1704 u_rms 0.04, "
+                               f"diagnostics every 100 steps",
+                   "nodes": N, "lattice": "D3Q19", "storage": "f32"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "lbm::d3q19::step_kernel<float>",
+                     "kernel_ms": round(kern * 1e3, 4), "bytes_per_node": bytes_per_node,
+                     "kernel_source_sha": sha},
+        "diagnostics": {"mass": diag["mass"], "ke": diag["ke"], "umax": diag["umax"], "nonfinite": diag["nonfinite"]},
+    }
+
+    if not args.no_extra:
+        extra = {}
+        m = 384
+        log(f"generating the {m}^3 initial field")
+        u3 = synth.spectrum_velocity((m, m, m), seed=1704, u_rms=0.04)
+        rho_u3 = lbm.rho_u_field(np.zeros((m, m, m)), u3)
+        del u3
+        for name, st, bpn in (("f16", capi.LBM_F16, 19 * 2 * 2 + 8), ("bf16", capi.LBM_BF16, 19 * 2 * 2 + 8),
+                              ("f32", capi.LBM_F32, 19 * 4 * 2 + 8)):
+            s3 = lbm.LBM(les_params(capi, m, st), rho_u3)
+            steps3 = max(1, args.steps // 2)
+            log(f"{name} {m}^3: {args.warmup} warmup + {steps3} timed steps")
+            w3, k3, d3 = time_run(s3, steps3, args.warmup)
+            s3.close()
+            del s3
+            torch.cuda.empty_cache()
+            extra[f"les384_{name}"] = {"MLUPS": round(m ** 3 * steps3 / w3 / 1e6, 1),
+                                       "ms_per_step": round(w3 / steps3 * 1e3, 4),
+                                       "kernel_ms": round(k3 * 1e3, 4), "bytes_per_node": bpn,
+                                       "hbm_frac": round(bpn * m ** 3 / k3 / 1e9 / HBM_PEAK_GBS, 4),
+                                       "ke": d3["ke"], "nonfinite": d3["nonfinite"]}
+        del rho_u3
+        torch.cuda.empty_cache()
+        result["extra"] = extra
+
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a slab")
+        result["cpu_baseline"] = cpu_baseline(u)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) MRT lattice Boltzmann library with the Yu and
+ * Chai strain-rate formulas.
+ *
+ * Method: Zhang, Huang, Wang, Shi, "The computation of strain rate tensor in
+ * multiple-relaxation-time lattice Boltzmann model" (arXiv 1704.07559).
+ *   - the He-Luo D3Q19 MRT model of Section 2 (Eqs. mrteq, edf, omega, HeLuoD3Q19, the
+ *     matrix T, Eqs. meq, sD3Q15, sD3Q15meaning);
+ *   - the Yu formula (Eq. LuoS) and the Chai formula (Eq. ChaiS) of Section 3;
+ *   - the D2Q9 variant that Section 5.3 says the Chai formula covers, with the Yu-type
+ *     D2Q9 formula obtained by the route of Section 5.4.
+ *
+ * Conventions shared by every entry point
+ *   - All arrays are structure-of-arrays, x fastest: element (c, z, y, x) of a field with
+ *     C components sits at  c*N + (z*ny + y)*nx + x,  N = nx*ny*nz.
+ *   - Populations are the deviations g_i = f_i - w_i rho0 (the delta-rho form of Eq. edf),
+ *     i in the velocity order of Eq. HeLuoD3Q19 (D3Q19) or (0, E, N, W, S, NE, NW, SW, SE)
+ *     (D2Q9). "Canonical" populations are the pre-collision g_i(x, n) of Eq. mrteq. The
+ *     library keeps its own internal layout in the two state buffers; only
+ *     lbm_get_populations / lbm_set_populations / lbm_init convert.
+ *   - Strain fields hold 6 components (xx, yy, zz, xy, yz, xz) for D3Q19 and 3 components
+ *     (xx, yy, xy) for D2Q9, of the strain of the pre-collision state.
+ *   - Lattice units: delta_x = delta_t = 1, c_s^2 = 1/3.
+ *   - Every pointer argument named as a field is a DEVICE pointer, caller-owned, and must
+ *     stay valid while the context uses it. Buffers must be 256-byte aligned. No entry
+ *     point allocates device memory except lbm_init (a small reduction scratch) and none
+ *     frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call is
+ *     asynchronous on that stream, except where a host result is returned (lbm_reduce,
+ *     lbm_strain_loss_seed), which synchronise the stream before returning.
+ *   - No C++ exception crosses the ABI. Every call returns an lbm_status; on failure
+ *     lbm_last_error() gives a message (thread-local). Arguments are validated before any
+ *     launch; a kernel-launch failure maps to LBM_EHIP.
+ *   - A context is not thread-safe; use one per stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,       /* invalid argument (sizes, alignment, aliasing, enum values) */
+  LBM_EHIP = -2,         /* a HIP runtime call or kernel launch failed */
+  LBM_ENOMEM = -3,       /* device scratch allocation failed */
+  LBM_ESTATE = -4,       /* call not valid in the context's state (e.g. no force field) */
+  LBM_ENONFINITE = -5,   /* lbm_reduce found non-finite populations */
+  LBM_EUNSUPPORTED = -6  /* valid but not provided combination (e.g. D2Q9 adjoint) */
+} lbm_status;
+
+typedef enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 } lbm_lattice;
+typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
+typedef enum { LBM_STRAIN_NONE = 0, LBM_STRAIN_YU = 1, LBM_STRAIN_CHAI = 2 } lbm_strain_kind;
+typedef enum { LBM_VISC_CONST = 0, LBM_VISC_SMAGORINSKY = 1, LBM_VISC_POWERLAW = 2 } lbm_visc_kind;
+
+/*
+ * Model parameters.
+ *  s[]        diagonal of Lambda-hat (Eq. sD3Q15): 19 entries for D3Q19, the first 9 for
+ *             D2Q9 (rates of rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy). The s_nu slots
+ *             (D3Q19: 9, 11, 13, 14, 15; D2Q9: 7, 8) must hold one value, the initial s_nu.
+ *  omega_*    the free equilibrium coefficients of Eq. meq (paper: 3, -11/2, -1/2);
+ *             D3Q19 only.
+ *  visc_kind  LBM_VISC_CONST: s_nu fixed.  LBM_VISC_SMAGORINSKY: nu = nu0 + c_smag^2 |S|.
+ *             LBM_VISC_POWERLAW: nu = clamp(K_pl |S|^(n_pl-1), nu_min, nu_max), with
+ *             nu = nu_max (n_pl < 1) or nu_min (n_pl > 1) at |S| = 0. |S| = sqrt(2 S:S).
+ *             s_nu = 1/(3 nu + 1/2) relaxes the collision; the strain of the next step
+ *             uses the s_nu of the previous collision at the node (held in s_nu_field).
+ *  visc_strain which formula drives the viscosity (LBM_STRAIN_YU or LBM_STRAIN_CHAI).
+ *  walls_y    0: periodic in y. 1: halfway bounce-back walls at y = -1/2 and y = ny - 1/2.
+ *  force[3]   uniform body force (Guo forcing, j = sum c g + F/2) used when
+ *             force_field is NULL; force_field: device float[3*N] field, or NULL.
+ */
+typedef struct {
+  int lattice;       /* lbm_lattice */
+  int storage;       /* lbm_storage of the population buffers */
+  int nx, ny, nz;    /* nz = 1 for D2Q9 */
+  int walls_y;
+  double rho0;
+  double s[19];
+  double omega_eps, omega_epsj, omega_xx;
+  int visc_kind;     /* lbm_visc_kind */
+  int visc_strain;   /* lbm_strain_kind */
+  double nu0, c_smag, K_pl, n_pl, nu_min, nu_max;
+  double force[3];
+  const float* force_field;
+} lbm_params;
+
+/* Bytes of one population buffer (Q * N * element size) for these parameters, or 0 if the
+ * parameters are invalid. */
+size_t lbm_population_bytes(const lbm_params* p);
+
+/*
+ * Create a context over caller-owned device buffers and write the initial state.
+ *  f_a, f_b     two distinct population buffers of lbm_population_bytes(p) bytes.
+ *  s_nu_field   device float[N]; required unless visc_kind == LBM_VISC_CONST (may be NULL
+ *               then). Filled with the initial s_nu.
+ *  rho_u        device float[4*N]: planes delta_rho, u_x, u_y, u_z (u_z ignored for D2Q9);
+ *               NULL = fluid at rest. Initial populations are g^eq(delta_rho, rho0 u)
+ *               (the delta-rho form of Eq. edf).
+ *  grad_u       device float[9*N], plane a*3+b = d u_b / d x_a, or NULL. When given, the
+ *               non-equilibrium moments predicted by Eq. YuLuobasis are added (D3Q19: rows
+ *               1, 9, 11, 13, 14, 15; D2Q9: rows 1, 7, 8), so the strain of the initial
+ *               state equals the symmetric part of grad_u.
+ * Errors: LBM_EINVAL (bad sizes, alignment, aliasing, unequal s_nu slots), LBM_ENOMEM,
+ * LBM_EHIP. On error *out is NULL.
+ */
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, float* s_nu_field,
+                    const float* rho_u, const float* grad_u, void* stream);
+
+/*
+ * Advance nsteps steps of Eq. mrteq (collide with moment-space relaxation, Eq. mrteqvT,
+ * then pull streaming), one fused kernel per step.
+ *  S_out        device float[6*N] (D3Q19) / [3*N] (D2Q9) or NULL: receives, at every step,
+ *               the strain (formula `strain_kind`) of that step's pre-collision state; after
+ *               the call it holds the strain of the state at level n_end - 1.
+ *  strain_kind  LBM_STRAIN_YU or LBM_STRAIN_CHAI (ignored when S_out is NULL).
+ *  j_save       device float[nsteps*3*N] or NULL: step k writes the momentum
+ *               j = sum c g + F/2 used by its collision at offset k*3*N (for the adjoint).
+ */
+lbm_status lbm_step(lbm_ctx* ctx, int nsteps, float* S_out, int strain_kind, float* j_save, void* stream);
+
+/* Strain of the current pre-collision state by the Yu (Eq. LuoS) or Chai (Eq. ChaiS)
+ * formula, with the current s_nu field, into S_out (device float[6*N] / [3*N]). */
+lbm_status lbm_strain(lbm_ctx* ctx, int strain_kind, float* S_out, void* stream);
+
+/*
+ * Global diagnostics of the current state, accumulated in FP64 with a deterministic
+ * two-pass reduction. host_out (host memory, 8 doubles):
+ *   [0] sum delta_rho  [1..3] sum j (j includes F/2)  [4] sum |j|^2/(2 rho0)
+ *   [5] sum S:S (Yu, off-diagonals counted twice)  [6] max |j|/rho0  [7] count of
+ *   non-finite populations.
+ * Synchronises the stream. Returns LBM_ENONFINITE (after filling host_out) if [7] > 0.
+ */
+lbm_status lbm_reduce(lbm_ctx* ctx, double* host_out, void* stream);
+
+/* Current canonical pre-collision populations g_i(x, n) as FP32 (device float[Q*N]). */
+lbm_status lbm_get_populations(lbm_ctx* ctx, float* f_canon, void* stream);
+
+/* Replace the state by canonical populations (device float[Q*N]), rounded to the storage
+ * type. The s_nu field is left as it is. */
+lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f_canon, void* stream);
+
+/* Checkpoint support: lbm_state_bytes() bytes hold the internal population buffer and,
+ * for a variable viscosity, the s_nu field. save/load are device-to-device copies. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_save_state(lbm_ctx* ctx, void* dst, void* stream);
+lbm_status lbm_load_state(lbm_ctx* ctx, const void* src, void* stream);
+long long lbm_step_count(const lbm_ctx* ctx);
+lbm_status lbm_set_step_count(lbm_ctx* ctx, long long n);
+
+/*
+ * Discrete adjoint (D3Q19, constant viscosity, periodic or walls_y). For one forward step
+ * g^{n+1} = P C(g^n, F) (C the collision, P the pull streaming), given lam_in = dJ/dg^{n+1}
+ * (canonical layout, device float[19*N]) and j_n (device float[3*N], the momentum that
+ * step's collision used, as written by lbm_step's j_save), writes
+ *   lam_out = (dC/dg)^T P^T lam_in              (device float[19*N])
+ * and, if grad_force is not NULL, accumulates (dC/dF)^T P^T lam_in into it (device
+ * float[3*N], read-modify-write). lam_in and lam_out must not alias.
+ */
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const float* j_n, const float* lam_in, float* lam_out,
+                            float* grad_force, void* stream);
+
+/*
+ * Loss J = sum_x S:S of the current pre-collision state (Yu formula, which equals Chai,
+ * Section 5.1), its gradient dJ/dg into lam_out (device float[19*N], canonical), and, if
+ * grad_force is not NULL, dJ/dF (through j = sum c g + F/2) added into grad_force. J is
+ * accumulated in FP64 and written to *J_host. Synchronises the stream.
+ */
+lbm_status lbm_strain_loss_seed(lbm_ctx* ctx, float* lam_out, float* grad_force, double* J_host, void* stream);
+
+/*
+ * Adjoint of the initial state g^0 = g^eq(0, rho0 u0): grad_u0 (device float[3*N]) =
+ * sum_i lam0_i dg^eq_i/du at u0 (rho_u: device float[4*N] as given to lbm_init).
+ */
+lbm_status lbm_init_adjoint(lbm_ctx* ctx, const float* rho_u, const float* lam0, float* grad_u0, void* stream);
+
+void lbm_destroy(lbm_ctx* ctx);
+const char* lbm_status_string(int status);
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,360 @@
+// C ABI of the library (include/lbm.h): argument validation, the context, ping-pong of
+// the two population buffers and dispatch to the kernel launchers. No exception leaves
+// this file; every failure is an lbm_status plus a thread-local message.
+#include "../../include/lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+  lbm_params p;
+  int Q;
+  size_t elem;      // bytes per stored population
+  size_t pop_bytes; // Q * N * elem
+  Geo G;
+  ModelF M;
+  ViscF V;
+  ForceF F;
+  void* buf[2];
+  int cur;          // buffer holding the current internal state
+  float* snu;       // lagged s_nu field (variable viscosity) or nullptr
+  double* scratch;  // reduction partials (kReduceBlocks * 8) + result (8)
+  long long step;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbm_status fail(lbm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+lbm_status hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return LBM_EHIP;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+size_t elem_size(int storage) {
+  switch (storage) {
+    case LBM_F32: return 4;
+    case LBM_F16: return 2;
+    case LBM_BF16: return 2;
+    default: return 0;
+  }
+}
+
+// Validate the parameters; on success fill Q and N.
+lbm_status check_params(const lbm_params* p, int* Q, size_t* N) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->lattice != LBM_D3Q19 && p->lattice != LBM_D2Q9) return fail(LBM_EINVAL, "lattice must be LBM_D3Q19 or LBM_D2Q9");
+  if (elem_size(p->storage) == 0) return fail(LBM_EINVAL, "storage must be LBM_F32, LBM_F16 or LBM_BF16");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 requires nz == 1");
+  const size_t n = static_cast<size_t>(p->nx) * p->ny * p->nz;
+  if (n >= (size_t(1) << 31)) return fail(LBM_EINVAL, "nx*ny*nz must be below 2^31 nodes");
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be positive and finite");
+  const int q = p->lattice;
+  for (int k = 0; k < q; ++k)
+    if (!std::isfinite(p->s[k])) return fail(LBM_EINVAL, "relaxation rates must be finite");
+  if (q == 19) {
+    const double sn = p->s[9];
+    if (p->s[11] != sn || p->s[13] != sn || p->s[14] != sn || p->s[15] != sn)
+      return fail(LBM_EINVAL, "D3Q19: the s_nu slots 9, 11, 13, 14, 15 must be equal");
+  } else {
+    if (p->s[8] != p->s[7]) return fail(LBM_EINVAL, "D2Q9: the s_nu slots 7 and 8 must be equal");
+  }
+  const int snu_slot = (q == 19) ? 9 : 7;
+  if (!(p->s[snu_slot] > 0.0)) return fail(LBM_EINVAL, "s_nu must be positive");
+  if (p->visc_kind < LBM_VISC_CONST || p->visc_kind > LBM_VISC_POWERLAW) return fail(LBM_EINVAL, "bad visc_kind");
+  if (p->visc_kind != LBM_VISC_CONST && p->visc_strain != LBM_STRAIN_YU && p->visc_strain != LBM_STRAIN_CHAI)
+    return fail(LBM_EINVAL, "visc_strain must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
+  if (p->visc_kind == LBM_VISC_SMAGORINSKY && !(p->nu0 >= 0.0)) return fail(LBM_EINVAL, "nu0 must be >= 0");
+  if (p->visc_kind == LBM_VISC_POWERLAW &&
+      !(p->K_pl > 0.0 && p->nu_min > 0.0 && p->nu_max >= p->nu_min && std::isfinite(p->n_pl)))
+    return fail(LBM_EINVAL, "power law needs K_pl > 0 and 0 < nu_min <= nu_max");
+  if (p->walls_y != 0 && p->walls_y != 1) return fail(LBM_EINVAL, "walls_y must be 0 or 1");
+  if (p->walls_y && p->ny < 2) return fail(LBM_EINVAL, "walls_y needs ny >= 2");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->force[a])) return fail(LBM_EINVAL, "force must be finite");
+  if (p->force_field && !aligned(p->force_field, 4)) return fail(LBM_EINVAL, "force_field must be 4-byte aligned");
+  *Q = q;
+  *N = n;
+  return LBM_OK;
+}
+
+void fill_model(lbm_ctx* c) {
+  const lbm_params& p = c->p;
+  c->G.nx = p.nx;
+  c->G.ny = p.ny;
+  c->G.nz = p.nz;
+  c->G.N = static_cast<unsigned>(static_cast<size_t>(p.nx) * p.ny * p.nz);
+  c->G.walls = p.walls_y;
+  c->M.rho0 = static_cast<float>(p.rho0);
+  c->M.inv_rho0 = static_cast<float>(1.0 / p.rho0);
+  for (int k = 0; k < 19; ++k) c->M.s[k] = static_cast<float>(k < c->Q ? p.s[k] : 0.0);
+  c->M.om_eps = static_cast<float>(p.omega_eps);
+  c->M.om_epsj = static_cast<float>(p.omega_epsj);
+  c->M.om_xx = static_cast<float>(p.omega_xx);
+  c->V.kind = p.visc_kind;
+  c->V.drive_chai = p.visc_strain == LBM_STRAIN_CHAI;
+  c->V.nu0 = static_cast<float>(p.nu0);
+  c->V.csmag2 = static_cast<float>(p.c_smag * p.c_smag);
+  c->V.Kpl = static_cast<float>(p.K_pl);
+  c->V.npl = static_cast<float>(p.n_pl);
+  c->V.numin = static_cast<float>(p.nu_min);
+  c->V.numax = static_cast<float>(p.nu_max);
+  c->F.field = p.force_field;
+  for (int a = 0; a < 3; ++a) c->F.F[a] = static_cast<float>(p.force[a]);
+  if (p.force_field) c->F.mode = 2;
+  else if (p.force[0] != 0.0 || p.force[1] != 0.0 || p.force[2] != 0.0) c->F.mode = 1;
+  else c->F.mode = 0;
+}
+
+bool is3d(const lbm_ctx* c) { return c->Q == 19; }
+
+lbm_status check_ctx(const lbm_ctx* c) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  return LBM_OK;
+}
+
+lbm_status check_field(const void* p, const char* name) {
+  if (!p) return fail(LBM_EINVAL, std::string(name) + " is NULL");
+  if (!aligned(p, 4)) return fail(LBM_EINVAL, std::string(name) + " must be 4-byte aligned");
+  return LBM_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_population_bytes(const lbm_params* p) {
+  int Q;
+  size_t N;
+  if (check_params(p, &Q, &N) != LBM_OK) return 0;
+  return static_cast<size_t>(Q) * N * elem_size(p->storage);
+}
+
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, float* s_nu_field, const float* rho_u,
+                    const float* grad_u, void* stream) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int Q;
+  size_t N;
+  lbm_status st = check_params(p, &Q, &N);
+  if (st != LBM_OK) return st;
+  const size_t bytes = static_cast<size_t>(Q) * N * elem_size(p->storage);
+  if (!f_a || !f_b) return fail(LBM_EINVAL, "population buffers must not be NULL");
+  if (!aligned(f_a, 256) || !aligned(f_b, 256)) return fail(LBM_EINVAL, "population buffers must be 256-byte aligned");
+  {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(f_a), b = reinterpret_cast<uintptr_t>(f_b);
+    if ((a < b ? b - a : a - b) < bytes) return fail(LBM_EINVAL, "population buffers overlap");
+  }
+  if (p->visc_kind != LBM_VISC_CONST && (st = check_field(s_nu_field, "s_nu_field")) != LBM_OK) return st;
+  if (s_nu_field && !aligned(s_nu_field, 4)) return fail(LBM_EINVAL, "s_nu_field must be 4-byte aligned");
+  if (rho_u && !aligned(rho_u, 4)) return fail(LBM_EINVAL, "rho_u must be 4-byte aligned");
+  if (grad_u && !aligned(grad_u, 4)) return fail(LBM_EINVAL, "grad_u must be 4-byte aligned");
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_ENOMEM, "host allocation of the context failed");
+  c->p = *p;
+  c->Q = Q;
+  c->elem = elem_size(p->storage);
+  c->pop_bytes = bytes;
+  c->buf[0] = f_a;
+  c->buf[1] = f_b;
+  c->cur = 0;
+  c->snu = (p->visc_kind != LBM_VISC_CONST) ? s_nu_field : nullptr;
+  c->step = 0;
+  fill_model(c);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&c->scratch), sizeof(double) * (kReduceBlocks + 1) * kReduceVals);
+  if (e != hipSuccess) {
+    delete c;
+    (void)hipGetLastError();
+    return fail(LBM_ENOMEM, std::string("hipMalloc of the reduction scratch failed: ") + hipGetErrorString(e));
+  }
+  const hipStream_t s = as_stream(stream);
+  e = is3d(c) ? d3q19::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s)
+              : d2q9::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s);
+  if (e != hipSuccess) {
+    (void)hipFree(c->scratch);
+    delete c;
+    return hip_fail(e, "lbm_init");
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float* j_save, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  if (S_out && !aligned(S_out, 4)) return fail(LBM_EINVAL, "S_out must be 4-byte aligned");
+  if (S_out && strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
+    return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
+  if (j_save && !aligned(j_save, 4)) return fail(LBM_EINVAL, "j_save must be 4-byte aligned");
+  if (j_save && !is3d(c)) return fail(LBM_EUNSUPPORTED, "j_save is provided for D3Q19 only");
+  const hipStream_t s = as_stream(stream);
+  for (int n = 0; n < nsteps; ++n) {
+    StepIO io;
+    io.src = c->buf[c->cur];
+    io.dst = c->buf[1 - c->cur];
+    io.snu = c->snu;
+    io.S_out = S_out;
+    io.emit = S_out ? strain_kind : 0;
+    io.j_save = j_save ? j_save + static_cast<size_t>(n) * 3 * c->G.N : nullptr;
+    hipError_t e = is3d(c) ? d3q19::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s)
+                           : d2q9::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step");
+    c->cur = 1 - c->cur;
+    c->step += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_strain(lbm_ctx* c, int strain_kind, float* S_out, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if ((st = check_field(S_out, "S_out")) != LBM_OK) return st;
+  if (strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
+    return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
+  const hipStream_t s = as_stream(stream);
+  hipError_t e = is3d(c) ? d3q19::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s)
+                         : d2q9::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_strain");
+}
+
+lbm_status lbm_reduce(lbm_ctx* c, double* host_out, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!host_out) return fail(LBM_EINVAL, "host_out is NULL");
+  const hipStream_t s = as_stream(stream);
+  double* partials = c->scratch;
+  double* dout = c->scratch + static_cast<size_t>(kReduceBlocks) * kReduceVals;
+  hipError_t e = is3d(c) ? d3q19::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s)
+                         : d2q9::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s);
+  if (e != hipSuccess) return hip_fail(e, "lbm_reduce");
+  e = hipMemcpyAsync(host_out, dout, sizeof(double) * kReduceVals, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "lbm_reduce copy");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "lbm_reduce sync");
+  if (host_out[7] > 0.0) return fail(LBM_ENONFINITE, "non-finite populations in the state");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, float* f_canon, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if ((st = check_field(f_canon, "f_canon")) != LBM_OK) return st;
+  const hipStream_t s = as_stream(stream);
+  hipError_t e = is3d(c) ? d3q19::launch_get(c->p.storage, c->G, c->buf[c->cur], f_canon, s)
+                         : d2q9::launch_get(c->p.storage, c->G, c->buf[c->cur], f_canon, s);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_get_populations");
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const float* f_canon, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if ((st = check_field(f_canon, "f_canon")) != LBM_OK) return st;
+  const hipStream_t s = as_stream(stream);
+  hipError_t e = is3d(c) ? d3q19::launch_set(c->p.storage, c->G, c->buf[c->cur], f_canon, s)
+                         : d2q9::launch_set(c->p.storage, c->G, c->buf[c->cur], f_canon, s);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_set_populations");
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  return c->pop_bytes + (c->snu ? sizeof(float) * c->G.N : 0);
+}
+
+lbm_status lbm_save_state(lbm_ctx* c, void* dst, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!dst || !aligned(dst, 4)) return fail(LBM_EINVAL, "dst must be a 4-byte aligned device pointer");
+  const hipStream_t s = as_stream(stream);
+  hipError_t e = hipMemcpyAsync(dst, c->buf[c->cur], c->pop_bytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && c->snu)
+    e = hipMemcpyAsync(static_cast<char*>(dst) + c->pop_bytes, c->snu, sizeof(float) * c->G.N, hipMemcpyDeviceToDevice, s);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_save_state");
+}
+
+lbm_status lbm_load_state(lbm_ctx* c, const void* src, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!src || !aligned(src, 4)) return fail(LBM_EINVAL, "src must be a 4-byte aligned device pointer");
+  const hipStream_t s = as_stream(stream);
+  hipError_t e = hipMemcpyAsync(c->buf[c->cur], src, c->pop_bytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && c->snu)
+    e = hipMemcpyAsync(c->snu, static_cast<const char*>(src) + c->pop_bytes, sizeof(float) * c->G.N, hipMemcpyDeviceToDevice, s);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_load_state");
+}
+
+long long lbm_step_count(const lbm_ctx* c) { return c ? c->step : -1; }
+
+lbm_status lbm_set_step_count(lbm_ctx* c, long long n) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (n < 0) return fail(LBM_EINVAL, "step count must be >= 0");
+  c->step = n;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* c, const float* j_n, const float* lam_in, float* lam_out, float* grad_force,
+                            void* stream) {
+  (void)j_n; (void)lam_in; (void)lam_out; (void)grad_force; (void)stream;
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  return fail(LBM_EUNSUPPORTED, "adjoint not available in this build");
+}
+
+lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, double* J_host, void* stream) {
+  (void)lam_out; (void)grad_force; (void)J_host; (void)stream;
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  return fail(LBM_EUNSUPPORTED, "adjoint not available in this build");
+}
+
+lbm_status lbm_init_adjoint(lbm_ctx* c, const float* rho_u, const float* lam0, float* grad_u0, void* stream) {
+  (void)rho_u; (void)lam0; (void)grad_u0; (void)stream;
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  return fail(LBM_EUNSUPPORTED, "adjoint not available in this build");
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->scratch) (void)hipFree(c->scratch);
+  delete c;
+}
+
+const char* lbm_status_string(int s) {
+  switch (s) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_EINVAL: return "LBM_EINVAL: invalid argument";
+    case LBM_EHIP: return "LBM_EHIP: HIP runtime error";
+    case LBM_ENOMEM: return "LBM_ENOMEM: allocation failed";
+    case LBM_ESTATE: return "LBM_ESTATE: invalid in the current state";
+    case LBM_ENONFINITE: return "LBM_ENONFINITE: non-finite populations";
+    case LBM_EUNSUPPORTED: return "LBM_EUNSUPPORTED: unsupported combination";
+    default: return "unknown lbm_status";
+  }
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

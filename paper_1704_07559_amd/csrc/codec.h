@@ -1,0 +1,33 @@
+// Storage codec for population buffers. The stored quantity is already the deviation
+// g_i = f_i - w_i rho0 (the delta-rho form of the equilibrium, which the paper adopts to
+// limit round-off), so FP16/BF16 storage keeps only the small part of f. All arithmetic is
+// FP32; stores round to nearest even.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+template <typename S>
+struct Codec;
+
+template <>
+struct Codec<float> {
+  static __device__ __forceinline__ float load(const float* p) { return *p; }
+  static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+};
+
+template <>
+struct Codec<_Float16> {
+  static __device__ __forceinline__ float load(const _Float16* p) { return static_cast<float>(*p); }
+  // fptrunc float -> half rounds to nearest even (default rounding mode).
+  static __device__ __forceinline__ void store(_Float16* p, float v) { *p = static_cast<_Float16>(v); }
+};
+
+template <>
+struct Codec<__bf16> {
+  static __device__ __forceinline__ float load(const __bf16* p) { return static_cast<float>(*p); }
+  // fptrunc float -> bfloat rounds to nearest even.
+  static __device__ __forceinline__ void store(__bf16* p, float v) { *p = static_cast<__bf16>(v); }
+};
+
+}  // namespace lbm

@@ -1,0 +1,194 @@
+// Internal declarations shared by the kernels and the C ABI layer (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "codec.h"
+#include "static_for.h"
+
+namespace lbm {
+
+// Grid geometry. Fields are SoA with x fastest: element (c, z, y, x) at c*N + (z*ny+y)*nx + x.
+struct Geo {
+  int nx, ny, nz;
+  unsigned N;  // nx*ny*nz (< 2^31 elements per component)
+  int walls;   // halfway bounce-back at y = -1/2 and y = ny - 1/2
+};
+
+// Model constants in FP32.
+struct ModelF {
+  float rho0, inv_rho0;
+  float s[19];
+  float om_eps, om_epsj, om_xx;
+};
+
+struct ViscF {
+  int kind;        // 0 const, 1 Smagorinsky, 2 power law
+  int drive_chai;  // 1: the Chai strain drives the viscosity, 0: the Yu strain
+  float nu0, csmag2, Kpl, npl, numin, numax;
+};
+
+struct ForceF {
+  int mode;  // 0 none, 1 uniform, 2 field
+  float F[3];
+  const float* field;
+};
+
+// Node coordinates of the three source positions along each axis, indexed by c + 1:
+// the pull reads population i at x - c_i, so c = -1 -> x + 1, c = 0 -> x, c = +1 -> x - 1.
+struct Nbr {
+  unsigned xs[3], ys[3], zs[3];
+  unsigned self;
+};
+
+__device__ __forceinline__ Nbr neighbours(const Geo& G, int x, int y, int z) {
+  Nbr n;
+  const unsigned nx = G.nx, nxy = static_cast<unsigned>(G.nx) * G.ny;
+  n.xs[0] = (x == G.nx - 1) ? 0u : x + 1;
+  n.xs[1] = x;
+  n.xs[2] = (x == 0) ? nx - 1 : x - 1;
+  n.ys[0] = ((y == G.ny - 1) ? 0u : y + 1) * nx;
+  n.ys[1] = y * nx;
+  n.ys[2] = ((y == 0) ? G.ny - 1u : y - 1) * nx;
+  n.zs[0] = ((z == G.nz - 1) ? 0u : z + 1) * nxy;
+  n.zs[1] = z * nxy;
+  n.zs[2] = ((z == 0) ? G.nz - 1u : z - 1) * nxy;
+  n.self = n.zs[1] + n.ys[1] + x;
+  return n;
+}
+
+// True when population i arriving at row y crossed a y-wall (its source row y - c_y is
+// outside 0..ny-1); bounce-back then takes the opposite population of the same node.
+template <int CYI>
+__device__ __forceinline__ bool crosses_wall(const Geo& G, int y) {
+  if constexpr (CYI == 0) return false;
+  else if constexpr (CYI > 0) return G.walls && y == 0;
+  else return G.walls && y == G.ny - 1;
+}
+
+// Pull streaming (the left side of Eq. mrteq): canonical g_i(x, n) = post-collision
+// population i of node x - c_i (periodic), or of population opp(i) at x across a wall.
+template <class L, typename S>
+__device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, const Nbr& nb, int y,
+                                     float (&g)[L::Q]) {
+  static_for<L::Q>([&](auto ii) {
+    constexpr int i = ii;
+    const S* base = src + static_cast<size_t>(i) * G.N;
+    unsigned off = nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[L::cx(i) + 1];
+    if (crosses_wall<L::cy(i)>(G, y)) {
+      base = src + static_cast<size_t>(L::opp(i)) * G.N;
+      off = nb.self;
+    }
+    g[i] = Codec<S>::load(base + off);
+  });
+}
+
+// Inverse of pull: write canonical g_i(x) to the internal slot it is pulled from.
+template <class L, typename S>
+__device__ __forceinline__ void scatter(S* __restrict__ dst, const Geo& G, const Nbr& nb, int y,
+                                        const float (&g)[L::Q]) {
+  static_for<L::Q>([&](auto ii) {
+    constexpr int i = ii;
+    S* base = dst + static_cast<size_t>(i) * G.N;
+    unsigned off = nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[L::cx(i) + 1];
+    if (crosses_wall<L::cy(i)>(G, y)) {
+      base = dst + static_cast<size_t>(L::opp(i)) * G.N;
+      off = nb.self;
+    }
+    Codec<S>::store(base + off, g[i]);
+  });
+}
+
+// Store post-collision populations at the node itself (coalesced).
+template <int Q, typename S>
+__device__ __forceinline__ void store_local(S* __restrict__ dst, const Geo& G, unsigned self, const float (&g)[Q]) {
+  static_for<Q>([&](auto ii) {
+    constexpr int i = ii;
+    Codec<S>::store(dst + static_cast<size_t>(i) * G.N + self, g[i]);
+  });
+}
+
+// s_nu = 1 / (3 nu + 1/2) from the strain magnitude |S| = sqrt(2 S:S).
+__device__ __forceinline__ float viscous_rate(float SS, const ViscF& V) {
+  const float gamma = sqrtf(2.0f * SS);
+  float nu;
+  if (V.kind == 1) {
+    nu = V.nu0 + V.csmag2 * gamma;
+  } else {
+    if (gamma > 0.0f) nu = V.Kpl * powf(gamma, V.npl - 1.0f);
+    else nu = (V.npl < 1.0f) ? V.numax : ((V.npl > 1.0f) ? V.numin : V.Kpl);
+    nu = fminf(fmaxf(nu, V.numin), V.numax);
+  }
+  return 1.0f / (3.0f * nu + 0.5f);
+}
+
+// Launch shape for the node-parallel kernels: one thread per node, 256-thread blocks of
+// (TX, TY) nodes with TX a power of two covering x, grid (ceil(nx/TX), ceil(ny/TY), nz).
+struct Launch {
+  dim3 grid, block;
+};
+
+inline Launch node_launch(const Geo& G) {
+  int tx = 1;
+  while (tx < G.nx && tx < 256) tx *= 2;
+  int ty = 256 / tx;
+  int py = 1;
+  while (py < G.ny) py *= 2;
+  if (ty > py) ty = py;
+  Launch L;
+  L.block = dim3(tx, ty, 1);
+  L.grid = dim3((G.nx + tx - 1) / tx, (G.ny + ty - 1) / ty, G.nz);
+  return L;
+}
+
+// Launch arguments of one step.
+struct StepIO {
+  const void* src;
+  void* dst;
+  float* snu;     // lagged s_nu field (variable viscosity) or nullptr
+  float* S_out;   // strain output or nullptr
+  int emit;       // 1 Yu, 2 Chai
+  float* j_save;  // 3*N or nullptr
+};
+
+// Reductions: 8 doubles per block, then one block sums the partials in a fixed order.
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceVals = 8;
+
+// ---- launchers (defined in the kernel translation units) -------------------------------
+namespace d3q19 {
+hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float* snu, const float* rho_u,
+                       const float* grad_u, hipStream_t);
+hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
+                       hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         int kind, float* S_out, hipStream_t);
+hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
+hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         double* partials, double* out, hipStream_t);
+hipError_t launch_adjoint_step(const Geo&, const ModelF&, const ForceF&, const float* j_n, const float* lam_in,
+                               float* lam_out, float* grad_force, hipStream_t);
+hipError_t launch_loss_seed(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, float* lam_out,
+                            float* grad_force, double* partials, double* out, hipStream_t);
+hipError_t launch_init_adjoint(const Geo&, const ModelF&, const float* rho_u, const float* lam0, float* grad_u0,
+                               hipStream_t);
+}  // namespace d3q19
+
+namespace d2q9 {
+hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float* snu, const float* rho_u,
+                       const float* grad_u, hipStream_t);
+hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
+                       hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         int kind, float* S_out, hipStream_t);
+hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
+hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         double* partials, double* out, hipStream_t);
+}  // namespace d2q9
+
+hipError_t launch_reduce_final(const double* partials, int nblocks, double* out, hipStream_t);
+
+}  // namespace lbm

@@ -1,0 +1,377 @@
+// D3Q19 kernels: initial state, the fused collide-stream-strain step, the strain query,
+// canonical gather/scatter and the diagnostics reduction.
+//
+// One thread owns one node. The step pulls the 19 post-collision populations of the
+// previous step from the neighbours (Eq. mrteq read backwards), forms the moments
+// m = T g (Section 2), the equilibrium moments (Eq. meq), the strain of this pre-collision
+// state by the Yu formula (Eq. LuoS) and/or the Chai formula (Eq. ChaiS), the new s_nu of
+// the viscosity model, relaxes in moment space (Eq. mrteqvT) and stores the 19
+// post-collision populations at the node itself. Loads are coalesced along x (shifted by
+// at most one element), stores are aligned and coalesced.
+#include <hip/hip_runtime.h>
+
+#include "d3q19.h"
+#include "internal.h"
+#include "reduce.h"
+
+namespace lbm {
+namespace d3q19 {
+
+struct Lat {
+  static constexpr int Q = 19;
+  static constexpr int cx(int i) { return CX[i]; }
+  static constexpr int cy(int i) { return CY[i]; }
+  static constexpr int cz(int i) { return CZ[i]; }
+  static constexpr int opp(int i) { return DV.opp[i]; }
+};
+
+constexpr bool is_nu_slot(int k) { return k == 9 || k == 11 || k == 13 || k == 14 || k == 15; }
+
+__device__ __forceinline__ void load_force(const ForceF& Fo, unsigned N, unsigned self, float& Fx, float& Fy,
+                                           float& Fz) {
+  if (Fo.mode == 1) {
+    Fx = Fo.F[0];
+    Fy = Fo.F[1];
+    Fz = Fo.F[2];
+  } else if (Fo.mode == 2) {
+    Fx = Fo.field[self];
+    Fy = Fo.field[N + self];
+    Fz = Fo.field[2 * static_cast<size_t>(N) + self];
+  } else {
+    Fx = Fy = Fz = 0.0f;
+  }
+}
+
+__device__ __forceinline__ void rates_with(const ModelF& M, float snu, float (&r)[Q]) {
+  static_for<Q>([&](auto ki) {
+    constexpr int k = ki;
+    r[k] = is_nu_slot(k) ? snu : M.s[k];
+  });
+}
+
+__device__ __forceinline__ float strain_sq(const float (&S)[6]) {
+  return S[0] * S[0] + S[1] * S[1] + S[2] * S[2] + 2.0f * (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
+}
+
+// ------------------------------------------------------------------------------------------
+// The fused step
+// ------------------------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, z);
+  const unsigned self = nb.self;
+
+  float g[Q];
+  pull<Lat>(static_cast<const S*>(io.src), G, nb, y, g);
+
+  const Pairs P = make_pairs(g);
+  const float drho = delta_rho(P);
+  float jx = momentum<0>(P), jy = momentum<1>(P), jz = momentum<2>(P);
+  float Fx, Fy, Fz;
+  load_force(Fo, G.N, self, Fx, Fy, Fz);
+  if (Fo.mode) {
+    jx = __builtin_fmaf(0.5f, Fx, jx);
+    jy = __builtin_fmaf(0.5f, Fy, jy);
+    jz = __builtin_fmaf(0.5f, Fz, jz);
+  }
+  const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
+
+  // Strain of the incoming state with the rates of the previous collision.
+  const float snu_prev = io.snu ? io.snu[self] : M.s[9];
+  const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
+  const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
+  float Syu[6], Sch[6];
+  if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
+  if (need_chai) {
+    float r[Q];
+    rates_with(M, snu_prev, r);
+    strain_chai(P, drho, jx, jy, jz, r, M.inv_rho0, Sch);
+  }
+  if (io.S_out) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) io.S_out[static_cast<size_t>(c) * G.N + self] = io.emit == 2 ? Sch[c] : Syu[c];
+  }
+
+  // Viscosity model -> s_nu of this collision (kept for the next step's strain).
+  float snu = M.s[9];
+  if (V.kind != 0) {
+    snu = viscous_rate(V.drive_chai ? strain_sq(Sch) : strain_sq(Syu), V);
+    io.snu[self] = snu;
+  }
+
+  // Relaxation in moment space: dm_k = -s_k (m_k - m_k^eq) + (1 - s_k/2) S_F,k.
+  float dm[Q];
+  dm[0] = 0.0f;
+  dm[3] = Fx;
+  dm[5] = Fy;
+  dm[7] = Fz;
+  static_for<Q>([&](auto ki) {
+    constexpr int k = ki;
+    if constexpr (k != 0 && k != 3 && k != 5 && k != 7) {
+      const float sk = is_nu_slot(k) ? snu : M.s[k];
+      dm[k] = -sk * n.m[k];
+    }
+  });
+  if (Fo.mode) {
+    float SF[Q];
+    force_moments(jx, jy, jz, Fx, Fy, Fz, M.inv_rho0, SF);
+    static_for<Q>([&](auto ki) {
+      constexpr int k = ki;
+      if constexpr (k != 0 && k != 3 && k != 5 && k != 7 && k < 16) {
+        const float sk = is_nu_slot(k) ? snu : M.s[k];
+        dm[k] = __builtin_fmaf(1.0f - 0.5f * sk, SF[k], dm[k]);
+      }
+    });
+  }
+  add_back_transform(dm, g);
+  store_local<Q>(static_cast<S*>(io.dst), G, self, g);
+
+  if (io.j_save) {
+    io.j_save[self] = jx;
+    io.j_save[G.N + self] = jy;
+    io.j_save[2 * static_cast<size_t>(G.N) + self] = jz;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Strain of the current state (read only)
+// ------------------------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
+                                                     int kind, float* S_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, z);
+  float g[Q];
+  pull<Lat>(buf, G, nb, y, g);
+  const Pairs P = make_pairs(g);
+  const float drho = delta_rho(P);
+  float jx = momentum<0>(P), jy = momentum<1>(P), jz = momentum<2>(P);
+  float Fx, Fy, Fz;
+  load_force(Fo, G.N, nb.self, Fx, Fy, Fz);
+  jx += 0.5f * Fx;
+  jy += 0.5f * Fy;
+  jz += 0.5f * Fz;
+  const float snu = snu_f ? snu_f[nb.self] : M.s[9];
+  float S6[6];
+  if (kind == 2) {
+    float r[Q];
+    rates_with(M, snu, r);
+    strain_chai(P, drho, jx, jy, jz, r, M.inv_rho0, S6);
+  } else {
+    const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
+    strain_yu(n, M.s[1], snu, M.inv_rho0, S6);
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) S_out[static_cast<size_t>(c) * G.N + nb.self] = S6[c];
+}
+
+// ------------------------------------------------------------------------------------------
+// Initial state g^eq(delta_rho, rho0 u) [+ Chapman-Enskog non-equilibrium part]
+// ------------------------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, float* snu, const float* rho_u,
+                                                   const float* grad_u) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, z);
+  const unsigned self = nb.self;
+  float drho = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
+  if (rho_u) {
+    drho = rho_u[self];
+    ux = rho_u[G.N + self];
+    uy = rho_u[2 * static_cast<size_t>(G.N) + self];
+    uz = rho_u[3 * static_cast<size_t>(G.N) + self];
+  }
+  float g[Q];
+  equilibrium(drho, M.rho0 * ux, M.rho0 * uy, M.rho0 * uz, M.inv_rho0, g);
+  if (grad_u) {
+    // d[a*3+b] = d j_b / d x_a; non-equilibrium moments of the Chapman-Enskog relations
+    // (Eq. YuLuobasis), every other row zero.
+    float d[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = M.rho0 * grad_u[static_cast<size_t>(k) * G.N + self];
+    const float div = d[0] + d[4] + d[8];
+    const float s1 = M.s[1], sn = M.s[9];
+    float mn[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) mn[k] = 0.0f;
+    mn[1] = -38.0f * div / (3.0f * s1);
+    mn[9] = -2.0f * (3.0f * d[0] - div) / (3.0f * sn);
+    mn[11] = -2.0f * (d[4] - d[8]) / (3.0f * sn);
+    mn[13] = -(d[1] + d[3]) / (3.0f * sn);
+    mn[14] = -(d[5] + d[7]) / (3.0f * sn);
+    mn[15] = -(d[2] + d[6]) / (3.0f * sn);
+    add_neq_from_moments(mn, g);
+  }
+  scatter<Lat>(buf, G, nb, y, g);
+  if (snu) snu[self] = M.s[9];
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* canon) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, z);
+  float g[Q];
+  pull<Lat>(buf, G, nb, y, g);
+  store_local<Q>(canon, G, nb.self, g);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void set_kernel(Geo G, S* buf, const float* canon) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, z);
+  float g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = canon[static_cast<size_t>(i) * G.N + nb.self];
+  scatter<Lat>(buf, G, nb, y, g);
+}
+
+// ------------------------------------------------------------------------------------------
+// Diagnostics: mass, momentum, kinetic energy, sum S:S (Yu), max |u|, non-finite count
+// ------------------------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
+                                                     double* partials) {
+  double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const unsigned stride = gridDim.x * blockDim.x;
+  for (unsigned idx = blockIdx.x * blockDim.x + threadIdx.x; idx < G.N; idx += stride) {
+    const int x = idx % G.nx;
+    const unsigned t = idx / G.nx;
+    const int y = t % G.ny;
+    const int z = t / G.ny;
+    const Nbr nb = neighbours(G, x, y, z);
+    float g[Q];
+    pull<Lat>(buf, G, nb, y, g);
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);
+    const Pairs P = make_pairs(g);
+    const float drho = delta_rho(P);
+    float jx = momentum<0>(P), jy = momentum<1>(P), jz = momentum<2>(P);
+    float Fx, Fy, Fz;
+    load_force(Fo, G.N, nb.self, Fx, Fy, Fz);
+    jx += 0.5f * Fx;
+    jy += 0.5f * Fy;
+    jz += 0.5f * Fz;
+    const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
+    float S6[6];
+    strain_yu(n, M.s[1], snu_f ? snu_f[nb.self] : M.s[9], M.inv_rho0, S6);
+    const double jj = static_cast<double>(jx) * jx + static_cast<double>(jy) * jy + static_cast<double>(jz) * jz;
+    acc[0] += drho;
+    acc[1] += jx;
+    acc[2] += jy;
+    acc[3] += jz;
+    acc[4] += jj * (0.5 / M.rho0);
+    double ss = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ss += (c < 3 ? 1.0 : 2.0) * static_cast<double>(S6[c]) * S6[c];
+    acc[5] += ss;
+    acc[6] = fmax(acc[6], sqrt(jj) / M.rho0);
+    acc[7] += bad;
+  }
+  block_reduce_store(acc, partials);
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+#define LBM_DISPATCH_STORAGE(storage, KERNEL, GRID, BLOCK, STREAM, ...)                                 \
+  do {                                                                                                 \
+    switch (storage) {                                                                                 \
+      case 0: hipLaunchKernelGGL(KERNEL<float>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;           \
+      case 1: hipLaunchKernelGGL(KERNEL<_Float16>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;        \
+      case 2: hipLaunchKernelGGL(KERNEL<__bf16>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;          \
+      default: return hipErrorInvalidValue;                                                            \
+    }                                                                                                  \
+  } while (0)
+
+template <typename S>
+static const S* cbuf(const void* p) {
+  return static_cast<const S*>(p);
+}
+
+hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,
+                       hipStream_t st) {
+  const Launch L = node_launch(G);
+  LBM_DISPATCH_STORAGE(storage, step_kernel, L.grid, L.block, st, G, M, V, Fo, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_strain(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
+                         const float* snu, int kind, float* S_out, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(strain_kernel<float>, L.grid, L.block, 0, st, G, M, Fo, cbuf<float>(buf), snu, kind, S_out); break;
+    case 1: hipLaunchKernelGGL(strain_kernel<_Float16>, L.grid, L.block, 0, st, G, M, Fo, cbuf<_Float16>(buf), snu, kind, S_out); break;
+    case 2: hipLaunchKernelGGL(strain_kernel<__bf16>, L.grid, L.block, 0, st, G, M, Fo, cbuf<__bf16>(buf), snu, kind, S_out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, const Geo& G, const ModelF& M, void* buf, float* snu, const float* rho_u,
+                       const float* grad_u, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(init_kernel<float>, L.grid, L.block, 0, st, G, M, static_cast<float*>(buf), snu, rho_u, grad_u); break;
+    case 1: hipLaunchKernelGGL(init_kernel<_Float16>, L.grid, L.block, 0, st, G, M, static_cast<_Float16*>(buf), snu, rho_u, grad_u); break;
+    case 2: hipLaunchKernelGGL(init_kernel<__bf16>, L.grid, L.block, 0, st, G, M, static_cast<__bf16*>(buf), snu, rho_u, grad_u); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_get(int storage, const Geo& G, const void* buf, float* canon, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(get_kernel<float>, L.grid, L.block, 0, st, G, cbuf<float>(buf), canon); break;
+    case 1: hipLaunchKernelGGL(get_kernel<_Float16>, L.grid, L.block, 0, st, G, cbuf<_Float16>(buf), canon); break;
+    case 2: hipLaunchKernelGGL(get_kernel<__bf16>, L.grid, L.block, 0, st, G, cbuf<__bf16>(buf), canon); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set(int storage, const Geo& G, void* buf, const float* canon, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(set_kernel<float>, L.grid, L.block, 0, st, G, static_cast<float*>(buf), canon); break;
+    case 1: hipLaunchKernelGGL(set_kernel<_Float16>, L.grid, L.block, 0, st, G, static_cast<_Float16*>(buf), canon); break;
+    case 2: hipLaunchKernelGGL(set_kernel<__bf16>, L.grid, L.block, 0, st, G, static_cast<__bf16*>(buf), canon); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
+                         const float* snu, double* partials, double* out, hipStream_t st) {
+  unsigned nb = (G.N + 255) / 256;
+  if (nb > static_cast<unsigned>(kReduceBlocks)) nb = kReduceBlocks;
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(reduce_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, Fo, cbuf<float>(buf), snu, partials); break;
+    case 1: hipLaunchKernelGGL(reduce_kernel<_Float16>, dim3(nb), dim3(256), 0, st, G, M, Fo, cbuf<_Float16>(buf), snu, partials); break;
+    case 2: hipLaunchKernelGGL(reduce_kernel<__bf16>, dim3(nb), dim3(256), 0, st, G, M, Fo, cbuf<__bf16>(buf), snu, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_final(partials, static_cast<int>(nb), out, st);
+}
+
+}  // namespace d3q19
+}  // namespace lbm

@@ -76,10 +76,13 @@ def spectrum_velocity(shape, seed: int = 1704, u_rms: float = 0.04, k0: float = 
     magnitude; the k = 0 and Nyquist modes are zeroed -> inverse FFT -> scaled so that
     sqrt(<u.u>/3) = u_rms.
     """
+    import scipy.fft as sfft
+
     nz, ny, nx = shape
     rng = np.random.default_rng(seed)
     noise = rng.standard_normal((3,) + tuple(shape))
-    uh = np.fft.fftn(noise, axes=(1, 2, 3))
+    uh = sfft.fftn(noise, axes=(1, 2, 3), workers=-1)
+    del noise
     kz = np.fft.fftfreq(nz, 1.0 / nz)
     ky = np.fft.fftfreq(ny, 1.0 / ny)
     kx = np.fft.fftfreq(nx, 1.0 / nx)
@@ -101,7 +104,10 @@ def spectrum_velocity(shape, seed: int = 1704, u_rms: float = 0.04, k0: float = 
     if nz % 2 == 0:
         nyq |= np.abs(KZ) == nz // 2
     amp[nyq] = 0.0
-    u = np.real(np.fft.ifftn(uh * amp[None], axes=(1, 2, 3)))
+    uh *= amp[None]
+    del amp, K, KX, KY, KZ, k2, kmag, safe, kdotu, E, nyq
+    u = np.real(sfft.ifftn(uh, axes=(1, 2, 3), workers=-1))
+    del uh
     rms = np.sqrt((u * u).sum(axis=0).mean() / 3.0)
     return np.ascontiguousarray(u * (u_rms / rms))
 

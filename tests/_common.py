@@ -1,0 +1,69 @@
+"""Shared helpers for the GPU parity tests: build matching oracle / library parameter sets
+from one spec, and the error measures the tolerances are stated in.
+
+Population error: elementwise |f_gpu - f_ref| / |f_ref| on the full distribution
+f = g + w_i rho0 (the stored g is the deviation). Strain error: max_{x,c} |dS_c(x)| divided
+by max_x ||S_ref(x)||_F (field-normalised, because components cross zero).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import d3q19 as od
+
+try:
+    import torch
+    HAS_GPU = torch.cuda.is_available()
+except Exception:  # pragma: no cover
+    HAS_GPU = False
+
+needs_gpu = pytest.mark.skipif(not HAS_GPU, reason="no GPU visible")
+
+
+def spec_params(shape, tau=0.8, rho0=1.0, s=None, visc="const", drive="yu", walls=False, force=None,
+                nu0=0.0, c_smag=0.1, K_pl=0.1, n_pl=1.0, nu_min=1e-3, nu_max=1.0, storage="f32",
+                omegas=(3.0, -5.5, -0.5)):
+    """Return (oracle Params, library Params, force tensor or None) for one spec."""
+    from paper_1704_07559_amd import capi
+    nz, ny, nx = shape
+    sv = od.default_rates(tau) if s is None else np.asarray(s, dtype=np.float64)
+    vk = {"const": capi.LBM_VISC_CONST, "smagorinsky": capi.LBM_VISC_SMAGORINSKY, "powerlaw": capi.LBM_VISC_POWERLAW}[visc]
+    dk = {"yu": capi.LBM_STRAIN_YU, "chai": capi.LBM_STRAIN_CHAI}[drive]
+    st = {"f32": capi.LBM_F32, "f16": capi.LBM_F16, "bf16": capi.LBM_BF16}[storage]
+    op = od.Params(rho0=rho0, s=sv.copy(), omega_eps=omegas[0], omega_epsj=omegas[1], omega_xx=omegas[2],
+                   visc_kind=visc, visc_strain=drive, nu0=nu0, c_smag=c_smag, K_pl=K_pl, n_pl=n_pl,
+                   nu_min=nu_min, nu_max=nu_max, walls_y=walls, force=force)
+    ftensor = None
+    fvec = (0.0, 0.0, 0.0)
+    if force is not None:
+        F = np.asarray(force, dtype=np.float64)
+        if F.shape == (3,):
+            fvec = tuple(float(v) for v in F)
+        else:
+            import torch
+            ftensor = torch.as_tensor(np.ascontiguousarray(F.reshape(3, -1), dtype=np.float32)).cuda()
+    cp = capi.Params(nx=nx, ny=ny, nz=nz, lattice=capi.LBM_D3Q19, storage=st, walls_y=int(walls), rho0=rho0,
+                     s=list(sv), omega_eps=omegas[0], omega_epsj=omegas[1], omega_xx=omegas[2], visc_kind=vk,
+                     visc_strain=dk, nu0=nu0, c_smag=c_smag, K_pl=K_pl, n_pl=n_pl, nu_min=nu_min, nu_max=nu_max,
+                     force=fvec, force_field=ftensor)
+    return op, cp, ftensor
+
+
+def pop_rel_err(g_gpu, g_ref, rho0=1.0, W=od.W):
+    q = g_ref.shape[0]
+    w = W.reshape((q,) + (1,) * (g_ref.ndim - 1)) * rho0
+    f_ref = g_ref + w
+    return float(np.max(np.abs((np.asarray(g_gpu, dtype=np.float64) + w) - f_ref) / np.abs(f_ref)))
+
+
+def strain_rel_err(S_gpu, S_ref):
+    S_ref = np.asarray(S_ref)
+    ncomp = S_ref.shape[0]
+    wts = np.array([1, 1, 1, 2, 2, 2] if ncomp == 6 else [1, 1, 2], dtype=np.float64)
+    frob = np.sqrt((wts.reshape((ncomp,) + (1,) * (S_ref.ndim - 1)) * S_ref**2).sum(axis=0))
+    return float(np.max(np.abs(np.asarray(S_gpu, dtype=np.float64) - S_ref)) / frob.max())
+
+
+def to_np(t):
+    return t.detach().cpu().numpy().astype(np.float64)

@@ -1,0 +1,71 @@
+"""Host-only checks of the C ABI: the library loads, exports every entry point that
+include/lbm.h declares, and validates arguments before touching the GPU."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def _declared():
+    text = (ROOT / "include" / "lbm.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("lbm_init", "lbm_step", "lbm_strain", "lbm_adjoint_step", "lbm_reduce", "lbm_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1704_07559_amd import capi
+    lib = ctypes.CDLL(capi.library_path())
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(capi.EXPORTED) == set(_declared())
+
+
+def test_population_bytes_and_validation():
+    from paper_1704_07559_amd import capi
+    s = [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, 1.25, 1.4, 1.25, 1.4, 1.25, 1.25, 1.25, 1.98, 1.98, 1.98]
+    p = capi.Params(nx=32, ny=16, nz=8, s=s)
+    assert capi.lbm_population_bytes(p) == 19 * 32 * 16 * 8 * 4
+    p.storage = capi.LBM_F16
+    assert capi.lbm_population_bytes(p) == 19 * 32 * 16 * 8 * 2
+    bad = capi.Params(nx=0, ny=16, nz=8, s=s)
+    assert capi.lbm_population_bytes(bad) == 0
+    uneq = list(s)
+    uneq[13] = 1.3
+    assert capi.lbm_population_bytes(capi.Params(nx=4, ny=4, nz=4, s=uneq)) == 0
+    assert capi.lbm_population_bytes(capi.Params(nx=4, ny=4, nz=2, lattice=capi.LBM_D2Q9, s=s)) == 0
+
+
+def test_init_rejects_bad_arguments_without_a_gpu():
+    """Every case here fails validation, which runs before any HIP call or launch."""
+    from paper_1704_07559_amd import capi
+    s = [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, 1.25, 1.4, 1.25, 1.4, 1.25, 1.25, 1.25, 1.98, 1.98, 1.98]
+    p = capi.Params(nx=8, ny=8, nz=8, s=s)
+    nbytes = capi.lbm_population_bytes(p)
+    cases = [
+        (p, 1 << 20, 1 << 20, None),                     # aliased buffers
+        (p, 1 << 20, (1 << 20) + nbytes // 2, None),     # overlapping buffers
+        (p, (1 << 20) + 4, 1 << 24, None),               # misaligned buffer
+        (p, None, 1 << 24, None),                        # missing buffer
+        (capi.Params(nx=8, ny=8, nz=8, s=s, visc_kind=capi.LBM_VISC_SMAGORINSKY), 1 << 20, 1 << 24, None),
+        (capi.Params(nx=8, ny=8, nz=8, s=s, visc_kind=capi.LBM_VISC_POWERLAW, K_pl=-1.0), 1 << 20, 1 << 24, 1 << 28),
+        (capi.Params(nx=8, ny=1, nz=8, s=s, walls_y=1), 1 << 20, 1 << 24, None),
+    ]
+    for params, a, b, snu in cases:
+        with pytest.raises(capi.LBMError) as e:
+            capi.lbm_init(params, a, b, snu, None, None, stream=0)
+        assert e.value.status == capi.LBM_EINVAL, capi.lbm_last_error()
+
+
+def test_status_strings():
+    from paper_1704_07559_amd import capi
+    assert capi.lbm_status_string(capi.LBM_OK) == "LBM_OK"
+    assert "invalid" in capi.lbm_status_string(capi.LBM_EINVAL)
