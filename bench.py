@@ -104,6 +104,76 @@ def time_run(sim, steps, warmup, reduce_every=100):
     return wall, kern, diag
 
 
+def copy_bandwidth(torch):
+    """Plain device-to-device copy of 1 GiB (read + write), for context."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * (1 << 30) / t / 1e9, 1)
+
+
+def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50):
+    """Strain-squared loss gradient on the 128^3 recipe (seeded spectrum velocity, uniform
+    random force U(-1e-6, 1e-6), tau_nu = 0.8, 500 steps, checkpoint every 50): wall time of
+    the forward pass and of the backward pass (recompute + adjoint), and the adjoint kernel
+    alone against HBM (algorithmic 200 B/node: 76 lambda in, 76 out, 12 j, 12 F, 24 grad_F)."""
+    from paper_1704_07559_amd import autograd as ag
+    shape = (n, n, n)
+    log(f"adjoint {n}^3: {nsteps} steps, checkpoint every {every}")
+    u0 = torch.as_tensor(synth.spectrum_velocity(shape, seed=1704, u_rms=0.04).astype(np.float32)).cuda()
+    F = torch.as_tensor(synth.uniform_random_force(shape, seed=7559, amp=1e-6).astype(np.float32)).cuda()
+    p = capi.Params(nx=n, ny=n, nz=n, s=rates(0.8))
+    # warm-up on a short problem (kernel loading, allocator)
+    u_w, F_w = u0.clone().requires_grad_(True), F.clone().requires_grad_(True)
+    ag.strain_loss(u_w, F_w, ag.StrainLossProblem(p, 2 * every, every)).backward()
+    u0.requires_grad_(True)
+    F.requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = ag.strain_loss(u0, F, ag.StrainLossProblem(p, nsteps, every))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    # adjoint kernel alone
+    N = n ** 3
+    sim = lbm.LBM(capi.Params(nx=n, ny=n, nz=n, s=rates(0.8), force_field=F.detach().reshape(3, N)))
+    jb = torch.zeros((1, 3, N), device="cuda")
+    sim.step(1, j_save=jb)
+    la = torch.randn((19, N), device="cuda")
+    lb = torch.empty_like(la)
+    gF = torch.zeros((3, N), device="cuda")
+    for _ in range(3):
+        capi.lbm_adjoint_step(sim.ctx, jb[0], la, lb, gF)
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        capi.lbm_adjoint_step(sim.ctx, jb[0], la, lb, gF)
+    e1.record()
+    torch.cuda.synchronize()
+    k_adj = e0.elapsed_time(e1) / 1e3 / reps
+    sim.close()
+    fwd, bwd = t1 - t0, t2 - t1
+    return {"J": J.item(), "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
+            "backward_over_forward": round(bwd / fwd, 3),
+            "adjoint_kernel_ms": round(k_adj * 1e3, 4),
+            "adjoint_hbm_frac": round(200 * N / k_adj / 1e9 / HBM_PEAK_GBS, 4),
+            "grad_u0_norm": float(u0.grad.norm()), "grad_F_norm": float(F.grad.norm())}
+
+
 def cpu_baseline(u_full, n_slab=64, steps=6):
     """FP64 oracle on a 256 x 256 x n_slab z-slab of the same initial field (periodic in the
     slab), Smagorinsky from Yu, ``steps`` steps."""
@@ -231,6 +301,11 @@ def main():
         del rho_u3
         torch.cuda.empty_cache()
         result["extra"] = extra
+
+    if not args.no_extra:
+        result.setdefault("extra", {})
+        result["extra"]["adjoint_c4"] = adjoint_run(torch, np, synth, capi, lbm, args.warmup)
+        result["extra"]["copy_GBps"] = copy_bandwidth(torch)
 
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a slab")

@@ -316,24 +316,55 @@ lbm_status lbm_set_step_count(lbm_ctx* c, long long n) {
 
 lbm_status lbm_adjoint_step(lbm_ctx* c, const float* j_n, const float* lam_in, float* lam_out, float* grad_force,
                             void* stream) {
-  (void)j_n; (void)lam_in; (void)lam_out; (void)grad_force; (void)stream;
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  return fail(LBM_EUNSUPPORTED, "adjoint not available in this build");
+  if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (c->V.kind != LBM_VISC_CONST) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for a constant viscosity");
+  if ((st = check_field(j_n, "j_n")) != LBM_OK) return st;
+  if ((st = check_field(lam_in, "lam_in")) != LBM_OK) return st;
+  if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
+  if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
+  {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(lam_in), b = reinterpret_cast<uintptr_t>(lam_out);
+    if ((a < b ? b - a : a - b) < sizeof(float) * 19 * static_cast<size_t>(c->G.N))
+      return fail(LBM_EINVAL, "lam_in and lam_out overlap");
+  }
+  hipError_t e = d3q19::launch_adjoint_step(c->G, c->M, c->F, j_n, lam_in, lam_out, grad_force, as_stream(stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step");
 }
 
 lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, double* J_host, void* stream) {
-  (void)lam_out; (void)grad_force; (void)J_host; (void)stream;
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  return fail(LBM_EUNSUPPORTED, "adjoint not available in this build");
+  if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (c->V.kind != LBM_VISC_CONST) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for a constant viscosity");
+  if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
+  if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
+  if (!J_host) return fail(LBM_EINVAL, "J_host is NULL");
+  const hipStream_t s = as_stream(stream);
+  double* partials = c->scratch;
+  double* dout = c->scratch + static_cast<size_t>(kReduceBlocks) * kReduceVals;
+  hipError_t e = d3q19::launch_loss_seed(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], lam_out, grad_force, partials,
+                                         dout, s);
+  if (e != hipSuccess) return hip_fail(e, "lbm_strain_loss_seed");
+  double out[kReduceVals];
+  e = hipMemcpyAsync(out, dout, sizeof(out), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "lbm_strain_loss_seed copy");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "lbm_strain_loss_seed sync");
+  *J_host = out[0];
+  return LBM_OK;
 }
 
 lbm_status lbm_init_adjoint(lbm_ctx* c, const float* rho_u, const float* lam0, float* grad_u0, void* stream) {
-  (void)rho_u; (void)lam0; (void)grad_u0; (void)stream;
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  return fail(LBM_EUNSUPPORTED, "adjoint not available in this build");
+  if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if ((st = check_field(rho_u, "rho_u")) != LBM_OK) return st;
+  if ((st = check_field(lam0, "lam0")) != LBM_OK) return st;
+  if ((st = check_field(grad_u0, "grad_u0")) != LBM_OK) return st;
+  hipError_t e = d3q19::launch_init_adjoint(c->G, c->M, rho_u, lam0, grad_u0, as_stream(stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init_adjoint");
 }
 
 void lbm_destroy(lbm_ctx* c) {

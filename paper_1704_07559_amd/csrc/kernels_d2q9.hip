@@ -1,25 +1,292 @@
-// D2Q9 kernels (placeholder launchers until the D2Q9 path lands).
+// D2Q9 kernels: the same fused pull-stream / collide / strain step as D3Q19 on the
+// nine-velocity lattice (Sections 5.3 and 5.4 of the paper), plus initial state, strain
+// query, canonical gather/scatter and the diagnostics reduction. One thread per node.
 #include <hip/hip_runtime.h>
 
+#include "d2q9.h"
 #include "internal.h"
+#include "reduce.h"
 
 namespace lbm {
 namespace d2q9 {
-hipError_t launch_init(int, const Geo&, const ModelF&, void*, float*, const float*, const float*, hipStream_t) {
-  return hipErrorNotSupported;
+
+__device__ __forceinline__ void load_force(const ForceF& Fo, unsigned N, unsigned self, float& Fx, float& Fy) {
+  if (Fo.mode == 1) {
+    Fx = Fo.F[0];
+    Fy = Fo.F[1];
+  } else if (Fo.mode == 2) {
+    Fx = Fo.field[self];
+    Fy = Fo.field[N + self];
+  } else {
+    Fx = Fy = 0.0f;
+  }
 }
-hipError_t launch_step(int, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&, hipStream_t) {
-  return hipErrorNotSupported;
+
+__device__ __forceinline__ void rates_with(const ModelF& M, float snu, float (&r)[Q]) {
+  static_for<Q>([&](auto ki) {
+    constexpr int k = ki;
+    r[k] = is_nu_slot(k) ? snu : M.s[k];
+  });
 }
-hipError_t launch_strain(int, const Geo&, const ModelF&, const ForceF&, const void*, const float*, int, float*,
-                         hipStream_t) {
-  return hipErrorNotSupported;
+
+__device__ __forceinline__ float strain_sq(const float (&S)[3]) { return S[0] * S[0] + S[1] * S[1] + 2.0f * S[2] * S[2]; }
+
+template <typename S>
+__global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, 0);
+  const unsigned self = nb.self;
+  float g[Q];
+  pull<Lat>(static_cast<const S*>(io.src), G, nb, y, g);
+  const Pairs P = make_pairs(g);
+  const float drho = delta_rho(P);
+  float jx = momentum<0>(P), jy = momentum<1>(P);
+  float Fx, Fy;
+  load_force(Fo, G.N, self, Fx, Fy);
+  if (Fo.mode) {
+    jx = __builtin_fmaf(0.5f, Fx, jx);
+    jy = __builtin_fmaf(0.5f, Fy, jy);
+  }
+  const Neq n = noneq_moments(P, drho, jx, jy, M.inv_rho0);
+  const float snu_prev = io.snu ? io.snu[self] : M.s[7];
+  const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
+  const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
+  float Syu[3], Sch[3];
+  if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
+  if (need_chai) {
+    float r[Q];
+    rates_with(M, snu_prev, r);
+    strain_chai(P, drho, jx, jy, r, M.inv_rho0, Sch);
+  }
+  if (io.S_out) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) io.S_out[static_cast<size_t>(c) * G.N + self] = io.emit == 2 ? Sch[c] : Syu[c];
+  }
+  float snu = M.s[7];
+  if (V.kind != 0) {
+    snu = viscous_rate(V.drive_chai ? strain_sq(Sch) : strain_sq(Syu), V);
+    io.snu[self] = snu;
+  }
+  float dm[Q];
+  dm[0] = 0.0f;
+  dm[3] = Fx;
+  dm[5] = Fy;
+  static_for<Q>([&](auto ki) {
+    constexpr int k = ki;
+    if constexpr (k != 0 && k != 3 && k != 5) dm[k] = -(is_nu_slot(k) ? snu : M.s[k]) * n.m[k];
+  });
+  if (Fo.mode) {
+    float SF[Q];
+    force_moments(jx, jy, Fx, Fy, M.inv_rho0, SF);
+    static_for<Q>([&](auto ki) {
+      constexpr int k = ki;
+      if constexpr (k != 0 && k != 3 && k != 5) {
+        const float sk = is_nu_slot(k) ? snu : M.s[k];
+        dm[k] = __builtin_fmaf(1.0f - 0.5f * sk, SF[k], dm[k]);
+      }
+    });
+  }
+  add_back_transform(dm, g);
+  store_local<Q>(static_cast<S*>(io.dst), G, self, g);
 }
-hipError_t launch_get(int, const Geo&, const void*, float*, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_set(int, const Geo&, void*, const float*, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_reduce(int, const Geo&, const ModelF&, const ForceF&, const void*, const float*, double*, double*,
-                         hipStream_t) {
-  return hipErrorNotSupported;
+
+template <typename S>
+__global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
+                                                     int kind, float* S_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, 0);
+  float g[Q];
+  pull<Lat>(buf, G, nb, y, g);
+  const Pairs P = make_pairs(g);
+  const float drho = delta_rho(P);
+  float Fx, Fy;
+  load_force(Fo, G.N, nb.self, Fx, Fy);
+  const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy;
+  const float snu = snu_f ? snu_f[nb.self] : M.s[7];
+  float S3[3];
+  if (kind == 2) {
+    float r[Q];
+    rates_with(M, snu, r);
+    strain_chai(P, drho, jx, jy, r, M.inv_rho0, S3);
+  } else {
+    strain_yu(noneq_moments(P, drho, jx, jy, M.inv_rho0), M.s[1], snu, M.inv_rho0, S3);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) S_out[static_cast<size_t>(c) * G.N + nb.self] = S3[c];
 }
+
+template <typename S>
+__global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, float* snu, const float* rho_u,
+                                                   const float* grad_u) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, 0);
+  const unsigned self = nb.self;
+  float drho = 0.f, ux = 0.f, uy = 0.f;
+  if (rho_u) {
+    drho = rho_u[self];
+    ux = rho_u[G.N + self];
+    uy = rho_u[2 * static_cast<size_t>(G.N) + self];
+  }
+  float g[Q];
+  equilibrium(drho, M.rho0 * ux, M.rho0 * uy, M.inv_rho0, g);
+  if (grad_u) {
+    // d[a*3+b] = d j_b / d x_a; inverse of the Yu-type formula (Chapman-Enskog state).
+    const size_t N = G.N;
+    const float dxx = M.rho0 * grad_u[0 * N + self], dxy = M.rho0 * grad_u[1 * N + self];
+    const float dyx = M.rho0 * grad_u[3 * N + self], dyy = M.rho0 * grad_u[4 * N + self];
+    const float sn = M.s[7];
+    float mn[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) mn[k] = 0.0f;
+    mn[1] = -2.0f * (dxx + dyy) / M.s[1];
+    mn[7] = -2.0f * (dxx - dyy) / (3.0f * sn);
+    mn[8] = -(dxy + dyx) / (3.0f * sn);
+    add_back_transform(mn, g);
+  }
+  scatter<Lat>(buf, G, nb, y, g);
+  if (snu) snu[self] = M.s[7];
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* canon) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, 0);
+  float g[Q];
+  pull<Lat>(buf, G, nb, y, g);
+  store_local<Q>(canon, G, nb.self, g);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void set_kernel(Geo G, S* buf, const float* canon) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr nb = neighbours(G, x, y, 0);
+  float g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = canon[static_cast<size_t>(i) * G.N + nb.self];
+  scatter<Lat>(buf, G, nb, y, g);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
+                                                     double* partials) {
+  double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const unsigned stride = gridDim.x * blockDim.x;
+  for (unsigned idx = blockIdx.x * blockDim.x + threadIdx.x; idx < G.N; idx += stride) {
+    const int x = idx % G.nx;
+    const int y = idx / G.nx;
+    const Nbr nb = neighbours(G, x, y, 0);
+    float g[Q];
+    pull<Lat>(buf, G, nb, y, g);
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);
+    const Pairs P = make_pairs(g);
+    const float drho = delta_rho(P);
+    float Fx, Fy;
+    load_force(Fo, G.N, nb.self, Fx, Fy);
+    const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy;
+    float S3[3];
+    strain_yu(noneq_moments(P, drho, jx, jy, M.inv_rho0), M.s[1], snu_f ? snu_f[nb.self] : M.s[7], M.inv_rho0, S3);
+    const double jj = static_cast<double>(jx) * jx + static_cast<double>(jy) * jy;
+    acc[0] += drho;
+    acc[1] += jx;
+    acc[2] += jy;
+    acc[4] += jj * (0.5 / M.rho0);
+    acc[5] += static_cast<double>(S3[0]) * S3[0] + static_cast<double>(S3[1]) * S3[1] +
+              2.0 * static_cast<double>(S3[2]) * S3[2];
+    acc[6] = fmax(acc[6], sqrt(jj) / M.rho0);
+    acc[7] += bad;
+  }
+  block_reduce_store(acc, partials);
+}
+
+template <typename S>
+static const S* cb(const void* p) {
+  return static_cast<const S*>(p);
+}
+
+hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,
+                       hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(step_kernel<float>, L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    case 1: hipLaunchKernelGGL(step_kernel<_Float16>, L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    case 2: hipLaunchKernelGGL(step_kernel<__bf16>, L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_strain(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
+                         const float* snu, int kind, float* S_out, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(strain_kernel<float>, L.grid, L.block, 0, st, G, M, Fo, cb<float>(buf), snu, kind, S_out); break;
+    case 1: hipLaunchKernelGGL(strain_kernel<_Float16>, L.grid, L.block, 0, st, G, M, Fo, cb<_Float16>(buf), snu, kind, S_out); break;
+    case 2: hipLaunchKernelGGL(strain_kernel<__bf16>, L.grid, L.block, 0, st, G, M, Fo, cb<__bf16>(buf), snu, kind, S_out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, const Geo& G, const ModelF& M, void* buf, float* snu, const float* rho_u,
+                       const float* grad_u, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(init_kernel<float>, L.grid, L.block, 0, st, G, M, static_cast<float*>(buf), snu, rho_u, grad_u); break;
+    case 1: hipLaunchKernelGGL(init_kernel<_Float16>, L.grid, L.block, 0, st, G, M, static_cast<_Float16*>(buf), snu, rho_u, grad_u); break;
+    case 2: hipLaunchKernelGGL(init_kernel<__bf16>, L.grid, L.block, 0, st, G, M, static_cast<__bf16*>(buf), snu, rho_u, grad_u); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_get(int storage, const Geo& G, const void* buf, float* canon, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(get_kernel<float>, L.grid, L.block, 0, st, G, cb<float>(buf), canon); break;
+    case 1: hipLaunchKernelGGL(get_kernel<_Float16>, L.grid, L.block, 0, st, G, cb<_Float16>(buf), canon); break;
+    case 2: hipLaunchKernelGGL(get_kernel<__bf16>, L.grid, L.block, 0, st, G, cb<__bf16>(buf), canon); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set(int storage, const Geo& G, void* buf, const float* canon, hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(set_kernel<float>, L.grid, L.block, 0, st, G, static_cast<float*>(buf), canon); break;
+    case 1: hipLaunchKernelGGL(set_kernel<_Float16>, L.grid, L.block, 0, st, G, static_cast<_Float16*>(buf), canon); break;
+    case 2: hipLaunchKernelGGL(set_kernel<__bf16>, L.grid, L.block, 0, st, G, static_cast<__bf16*>(buf), canon); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
+                         const float* snu, double* partials, double* out, hipStream_t st) {
+  unsigned nb = (G.N + 255) / 256;
+  if (nb > static_cast<unsigned>(kReduceBlocks)) nb = kReduceBlocks;
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(reduce_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, Fo, cb<float>(buf), snu, partials); break;
+    case 1: hipLaunchKernelGGL(reduce_kernel<_Float16>, dim3(nb), dim3(256), 0, st, G, M, Fo, cb<_Float16>(buf), snu, partials); break;
+    case 2: hipLaunchKernelGGL(reduce_kernel<__bf16>, dim3(nb), dim3(256), 0, st, G, M, Fo, cb<__bf16>(buf), snu, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_final(partials, static_cast<int>(nb), out, st);
+}
+
 }  // namespace d2q9
 }  // namespace lbm

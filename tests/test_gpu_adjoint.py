@@ -1,0 +1,120 @@
+"""Parity of the hand-written adjoint kernels (through the C ABI) with the FP64 adjoint
+oracle, and of the checkpointed torch.autograd.Function with the oracle gradient.
+
+Tolerances: adjoint quantities are compared field-normalised, max|d| / max|ref| <= 1e-5
+for one kernel call (FP32 against FP64) and <= 1e-4 for whole gradients over tens of
+steps; the directional derivatives (accumulated in FP64) to 1e-4 relative.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import adjoint as adj
+from oracle import d3q19 as od
+from tests._common import needs_gpu, spec_params, to_np
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a, dtype=np.float64) - b).max() / np.abs(b).max())
+
+
+def _state(shape, seed, p):
+    u = synth.random_vector(shape, seed=seed, scale=0.03)
+    g = od.init_populations(np.zeros(shape), u, p) + synth.random_state(19, shape, seed=seed + 1, scale=2e-3)
+    return g.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_adjoint_step_matches_oracle(walls):
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape = (5, 9, 70)
+    F = synth.uniform_random_force(shape, seed=3, amp=1e-4)
+    op, cp, _ = spec_params(shape, tau=0.7, walls=walls, force=F)
+    g = _state(shape, 1, op)
+    sim = lbm.LBM(cp)
+    sim.set_populations(torch.as_tensor(g.astype(np.float32)).cuda())
+    N = cp.N
+    jbuf = torch.empty((1, 3, N), device="cuda")
+    sim.step(1, j_save=jbuf)      # saves j of the collision of state g
+    lam_in = synth.random_state(19, shape, seed=4, scale=1.0)
+    lam_t = torch.as_tensor(lam_in.astype(np.float32)).cuda().reshape(19, N).contiguous()
+    lam_out = torch.empty_like(lam_t)
+    gF = torch.zeros((3, N), device="cuda")
+    capi.lbm_adjoint_step(sim.ctx, jbuf[0], lam_t, lam_out, gF)
+    ref_lam, ref_gF = adj.adjoint_step(lam_in.astype(np.float32).astype(np.float64), g, F, op)
+    assert _rel(to_np(lam_out).reshape(ref_lam.shape), ref_lam) < 1e-5
+    assert _rel(to_np(gF).reshape(ref_gF.shape), ref_gF) < 1e-5
+
+
+def test_loss_seed_and_init_adjoint_match_oracle():
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape = (4, 11, 67)
+    F = synth.uniform_random_force(shape, seed=5, amp=1e-4)
+    op, cp, _ = spec_params(shape, tau=0.75, force=F)
+    g = _state(shape, 6, op)
+    sim = lbm.LBM(cp)
+    sim.set_populations(torch.as_tensor(g.astype(np.float32)).cuda())
+    N = cp.N
+    lam = torch.empty((19, N), device="cuda")
+    gF = torch.zeros((3, N), device="cuda")
+    J = capi.lbm_strain_loss_seed(sim.ctx, lam, gF)
+    Jr, lamr, gFr = adj.strain_loss_seed(g, F, op)
+    assert abs(J - Jr) < 1e-5 * Jr
+    assert _rel(to_np(lam).reshape(lamr.shape), lamr) < 1e-5
+    assert _rel(to_np(gF).reshape(gFr.shape), gFr) < 1e-5
+    u0 = synth.random_vector(shape, seed=7, scale=0.04)
+    rho_u = torch.as_tensor(np.concatenate([np.zeros((1,) + shape), u0]).astype(np.float32)).cuda().reshape(4, N)
+    lam0 = synth.random_state(19, shape, seed=8, scale=1.0)
+    gu = torch.empty((3, N), device="cuda")
+    capi.lbm_init_adjoint(sim.ctx, rho_u, torch.as_tensor(lam0.astype(np.float32)).cuda().reshape(19, N), gu)
+    ref = adj.init_adjoint(lam0.astype(np.float32).astype(np.float64), u0.astype(np.float32).astype(np.float64), op)
+    assert _rel(to_np(gu).reshape(ref.shape), ref) < 1e-5
+
+
+def _c4(n):
+    shape = (n, n, n)
+    u0 = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
+    F = synth.uniform_random_force(shape, seed=7559, amp=1e-6)
+    return shape, u0, F
+
+
+@pytest.mark.parametrize("nsteps,every", [(50, 10), (23, 7)])
+def test_strain_loss_gradient_16_cubed(nsteps, every):
+    """The C4 recipe on 16^3: checkpointed GPU gradient against the FP64 oracle gradient."""
+    import torch
+    from paper_1704_07559_amd import autograd as ag
+    shape, u0, F = _c4(16)
+    op, cp, _ = spec_params(shape, tau=0.8)
+    Jr, gur, gFr = adj.gradient(u0, F, op, nsteps, every=every)
+    u0_t = torch.as_tensor(u0.astype(np.float32)).cuda().requires_grad_(True)
+    F_t = torch.as_tensor(F.astype(np.float32)).cuda().requires_grad_(True)
+    J = ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, nsteps, every))
+    J.backward()
+    assert abs(J.item() - Jr) < 1e-4 * Jr
+    gu, gF = to_np(u0_t.grad), to_np(F_t.grad)
+    assert _rel(gu, gur) < 1e-4
+    assert _rel(gF, gFr) < 1e-4
+    d = synth.random_vector(shape, seed=3, scale=1.0)
+    dd = torch.as_tensor(d).cuda()
+    assert abs((u0_t.grad.double() * dd).sum().item() - (gur * d).sum()) < 1e-4 * abs((gur * d).sum())
+    assert abs((F_t.grad.double() * dd).sum().item() - (gFr * d).sum()) < 1e-4 * abs((gFr * d).sum())
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    """Recompute is bit-identical on the GPU too: the gradient with checkpoints every 7 steps
+    equals the gradient with one checkpoint."""
+    import torch
+    from paper_1704_07559_amd import autograd as ag
+    shape, u0, F = _c4(12)
+    op, cp, _ = spec_params(shape, tau=0.8)
+    grads = []
+    for every in (21, 7):
+        u0_t = torch.as_tensor(u0.astype(np.float32)).cuda().requires_grad_(True)
+        F_t = torch.as_tensor(F.astype(np.float32)).cuda().requires_grad_(True)
+        ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, 21, every)).backward()
+        grads.append((u0_t.grad.clone(), F_t.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])

@@ -1,0 +1,108 @@
+"""Parity of the HIP D2Q9 path (through the C ABI) with the FP64 D2Q9 oracle.
+
+Same tolerances as the D3Q19 tests: populations 1e-5 relative on f = g + w rho0, strain
+1e-4 of the largest strain norm in the field."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import closed_forms as cf
+from oracle import d2q9 as od
+from tests._common import needs_gpu, pop_rel_err, strain_rel_err, to_np
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def _spec(shape, tau=0.8, s=None, visc="const", drive="yu", walls=False, force=None, **kw):
+    import torch
+    from paper_1704_07559_amd import capi
+    _, ny, nx = shape
+    sv = od.default_rates(tau) if s is None else np.asarray(s, dtype=np.float64)
+    op = od.Params(s=sv.copy(), visc_kind=visc, visc_strain=drive, walls_y=walls, force=force, **kw)
+    vk = {"const": 0, "smagorinsky": 1, "powerlaw": 2}[visc]
+    fvec, ft = (0.0, 0.0, 0.0), None
+    if force is not None:
+        F = np.asarray(force, dtype=np.float64)
+        if F.shape == (2,):
+            fvec = (float(F[0]), float(F[1]), 0.0)
+        else:
+            F3 = np.concatenate([F.reshape(2, -1), np.zeros((1, nx * ny))])
+            ft = torch.as_tensor(F3.astype(np.float32)).cuda().contiguous()
+    cp = capi.Params(nx=nx, ny=ny, nz=1, lattice=capi.LBM_D2Q9, walls_y=int(walls), s=list(sv) + [0.0] * 10,
+                     visc_kind=vk, visc_strain=1 if drive == "yu" else 2, force=fvec, force_field=ft,
+                     **{k: v for k, v in kw.items()})
+    return op, cp
+
+
+def _pop_err(g_gpu, g_ref):
+    return pop_rel_err(g_gpu, g_ref, 1.0, od.W)
+
+
+def test_init_then_gather_matches_oracle():
+    from paper_1704_07559_amd import lbm
+    shape = (1, 37, 300)
+    u = synth.random_vector(shape, seed=1, scale=0.03)[:2]
+    dr = synth.random_vector(shape, seed=2, scale=0.01)[0]
+    grad = np.stack([synth.random_vector(shape, seed=3, scale=3e-3), synth.random_vector(shape, seed=4, scale=3e-3),
+                     np.zeros((3,) + shape)])  # grad[a, b] = d u_b / d x_a; the z row and column unused
+    op, cp = _spec(shape, tau=0.7)
+    sim = lbm.LBM(cp, lbm.rho_u_field(dr, u), lbm.grad_field(grad))
+    assert _pop_err(to_np(sim.populations()), od.init_populations(dr, u, op, grad[:2, :2])) < 1e-6
+
+
+CASES = {
+    "const": dict(),
+    "srt": dict(s=np.full(9, 1 / 0.9)),
+    "smag_yu": dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2),
+    "powerlaw_chai_walls_force": dict(visc="powerlaw", drive="chai", K_pl=0.02, n_pl=0.6, walls=True,
+                                      force=np.array([1e-5, 0.0])),
+    "force_field": dict(force="field"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_steps_from_random_state(case):
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape = (1, 23, 131)
+    kw = dict(CASES[case])
+    if isinstance(kw.get("force"), str):
+        kw["force"] = synth.uniform_random_force(shape, seed=5, amp=1e-4)[:2]
+    op, cp = _spec(shape, **kw)
+    sim = lbm.LBM(cp)
+    g0 = synth.random_state(9, shape, seed=11, scale=3e-3).astype(np.float32).astype(np.float64)
+    sim.set_populations(torch.as_tensor(g0.astype(np.float32)).cuda())
+    ref = od.Simulation(op, g0)
+    S = torch.empty((3,) + shape, device="cuda")
+    for n in range(3):
+        S_chai = to_np(sim.strain(capi.LBM_STRAIN_CHAI))
+        sim.step(1, S_out=S, strain_kind=capi.LBM_STRAIN_YU)
+        Sy, Sc = ref.step(1)
+        assert strain_rel_err(to_np(S), Sy) < 1e-4, n
+        assert strain_rel_err(S_chai, Sc) < 1e-4, n
+        assert _pop_err(to_np(sim.populations()), ref.g) < 1e-5, n
+
+
+def test_taylor_green_64_squared_800_steps():
+    """Rotated Taylor-Green vortex on D2Q9, 64^2, diffusive-scaling parameters of the
+    convergence study (u0 = 0.025, 800 steps): strain every 100 steps against the oracle
+    and S_xy against the closed form."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    N, tau, u0, steps = 64, 0.8, 0.025, 800
+    shape = (1, N, N)
+    dr, u, gu = synth.tgv_rotated(shape, u0, 1.0)
+    op, cp = _spec(shape, tau=tau)
+    sim = lbm.LBM(cp, lbm.rho_u_field(dr, u[:2]), lbm.grad_field(gu))
+    ref = od.Simulation(op, od.init_populations(dr, u[:2], op, gu[:2, :2]))
+    for _ in range(8):
+        sim.step(100)
+        ref.step(100)
+        for kind, okind in ((capi.LBM_STRAIN_YU, "yu"), (capi.LBM_STRAIN_CHAI, "chai")):
+            assert strain_rel_err(to_np(sim.strain(kind)), ref.strain(okind)) < 1e-4
+    assert _pop_err(to_np(sim.populations()), ref.g) < 1e-5
+    exact = cf.tgv_rotated_strain(shape, u0, cf.nu_of_rate(1 / tau), steps)[3]
+    S = to_np(sim.strain(capi.LBM_STRAIN_YU))[2]
+    assert np.linalg.norm(S - exact) / np.linalg.norm(exact) < 2e-3
+    d = sim.reduce()
+    assert d["nonfinite"] == 0 and abs(d["mass"] - dr.sum()) < 1e-4 * np.abs(dr).sum()
