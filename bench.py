@@ -104,6 +104,29 @@ def time_run(sim, steps, warmup, reduce_every=100):
     return wall, kern, diag
 
 
+def channel_runs(torch, capi, lbm, steps, warmup):
+    """Power-law channel 128 x 128 x 512 (walls at y = -1/2 and 127.5, periodic x and z),
+    uniform body force 1e-6 along z, viscosity from the Chai strain, FP32, from rest; one
+    run per index n. Algorithmic bytes per node: 160 (populations + lagged s_nu)."""
+    out = {}
+    nx, ny, nz = 128, 128, 512
+    N = nx * ny * nz
+    gref = 1e-6 * ny / (2 * 0.1)   # wall shear rate of the Newtonian flow with nu = 0.1
+    for n_pl in (0.5, 1.0, 1.5):
+        p = capi.Params(nx=nx, ny=ny, nz=nz, s=rates(0.8), walls_y=1, force=(0.0, 0.0, 1e-6),
+                        visc_kind=capi.LBM_VISC_POWERLAW, visc_strain=capi.LBM_STRAIN_CHAI,
+                        K_pl=0.1 * gref ** (1 - n_pl), n_pl=n_pl, nu_min=1e-3, nu_max=1.0)
+        sim = lbm.LBM(p)
+        log(f"power-law channel n={n_pl}: {warmup} warmup + {steps} timed steps")
+        wall, kern, diag = time_run(sim, steps, warmup)
+        sim.close()
+        out[f"n{n_pl}"] = {"MLUPS": round(N * steps / wall / 1e6, 1), "kernel_ms": round(kern * 1e3, 4),
+                           "hbm_frac": round(160 * N / kern / 1e9 / HBM_PEAK_GBS, 4),
+                           "umax": diag["umax"], "nonfinite": diag["nonfinite"]}
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(torch):
     """Plain device-to-device copy of 1 GiB (read + write), for context."""
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -304,6 +327,7 @@ def main():
 
     if not args.no_extra:
         result.setdefault("extra", {})
+        result["extra"]["channel_powerlaw"] = channel_runs(torch, capi, lbm, max(1, args.steps // 2), args.warmup)
         result["extra"]["adjoint_c4"] = adjoint_run(torch, np, synth, capi, lbm, args.warmup)
         result["extra"]["copy_GBps"] = copy_bandwidth(torch)
 

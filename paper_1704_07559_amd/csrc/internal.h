@@ -37,6 +37,7 @@ struct ForceF {
 
 // Node coordinates of the three source positions along each axis, indexed by c + 1:
 // the pull reads population i at x - c_i, so c = -1 -> x + 1, c = 0 -> x, c = +1 -> x - 1.
+// Offsets are in elements of one population plane; `self` is the node itself.
 struct Nbr {
   unsigned xs[3], ys[3], zs[3];
   unsigned self;
@@ -58,6 +59,33 @@ __device__ __forceinline__ Nbr neighbours(const Geo& G, int x, int y, int z) {
   return n;
 }
 
+// The same offsets in bytes for elements of type S (N < 2^30 nodes keeps every byte offset
+// inside one population plane below 2^32).
+template <typename S>
+__device__ __forceinline__ Nbr in_bytes(const Nbr& n) {
+  constexpr unsigned b = sizeof(S);
+  Nbr r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.xs[k] = n.xs[k] * b;
+    r.ys[k] = n.ys[k] * b;
+    r.zs[k] = n.zs[k] * b;
+  }
+  r.self = n.self * b;
+  return r;
+}
+
+// Load/store at a wave-uniform base plus a 32-bit byte offset (the SGPR-base + VGPR-offset
+// addressing form of global memory instructions).
+template <typename S>
+__device__ __forceinline__ float load_at(const void* base, unsigned byte_off) {
+  return Codec<S>::load(reinterpret_cast<const S*>(static_cast<const char*>(base) + byte_off));
+}
+template <typename S>
+__device__ __forceinline__ void store_at(void* base, unsigned byte_off, float v) {
+  Codec<S>::store(reinterpret_cast<S*>(static_cast<char*>(base) + byte_off), v);
+}
+
 // True when population i arriving at row y crossed a y-wall (its source row y - c_y is
 // outside 0..ny-1); bounce-back then takes the opposite population of the same node.
 template <int CYI>
@@ -69,18 +97,22 @@ __device__ __forceinline__ bool crosses_wall(const Geo& G, int y) {
 
 // Pull streaming (the left side of Eq. mrteq): canonical g_i(x, n) = post-collision
 // population i of node x - c_i (periodic), or of population opp(i) at x across a wall.
-template <class L, typename S>
-__device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, const Nbr& nb, int y,
-                                     float (&g)[L::Q]) {
+// nb holds byte offsets for S. With WALLS false the bounce test is compiled out and every
+// population plane is addressed from a wave-uniform base.
+template <class L, typename S, bool WALLS = true>
+__device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, const Nbr& nb, int y, float (&g)[L::Q]) {
+  const char* cb = reinterpret_cast<const char*>(src);
+  const size_t plane = static_cast<size_t>(G.N) * sizeof(S);
   static_for<L::Q>([&](auto ii) {
     constexpr int i = ii;
-    const S* base = src + static_cast<size_t>(i) * G.N;
-    unsigned off = nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[L::cx(i) + 1];
-    if (crosses_wall<L::cy(i)>(G, y)) {
-      base = src + static_cast<size_t>(L::opp(i)) * G.N;
-      off = nb.self;
+    const unsigned off = nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[L::cx(i) + 1];
+    if constexpr (WALLS && L::cy(i) != 0) {
+      if (crosses_wall<L::cy(i)>(G, y)) {
+        g[i] = load_at<S>(cb + L::opp(i) * plane, nb.self);
+        return;
+      }
     }
-    g[i] = Codec<S>::load(base + off);
+    g[i] = load_at<S>(cb + i * plane, off);
   });
 }
 
@@ -88,24 +120,27 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, co
 template <class L, typename S>
 __device__ __forceinline__ void scatter(S* __restrict__ dst, const Geo& G, const Nbr& nb, int y,
                                         const float (&g)[L::Q]) {
+  char* cb = reinterpret_cast<char*>(dst);
+  const size_t plane = static_cast<size_t>(G.N) * sizeof(S);
   static_for<L::Q>([&](auto ii) {
     constexpr int i = ii;
-    S* base = dst + static_cast<size_t>(i) * G.N;
-    unsigned off = nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[L::cx(i) + 1];
     if (crosses_wall<L::cy(i)>(G, y)) {
-      base = dst + static_cast<size_t>(L::opp(i)) * G.N;
-      off = nb.self;
+      store_at<S>(cb + L::opp(i) * plane, nb.self, g[i]);
+    } else {
+      store_at<S>(cb + i * plane, nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[L::cx(i) + 1], g[i]);
     }
-    Codec<S>::store(base + off, g[i]);
   });
 }
 
-// Store post-collision populations at the node itself (coalesced).
+// Store post-collision populations at the node itself (coalesced); byte offset of S.
 template <int Q, typename S>
-__device__ __forceinline__ void store_local(S* __restrict__ dst, const Geo& G, unsigned self, const float (&g)[Q]) {
+__device__ __forceinline__ void store_local(S* __restrict__ dst, const Geo& G, unsigned self_bytes,
+                                            const float (&g)[Q]) {
+  char* cb = reinterpret_cast<char*>(dst);
+  const size_t plane = static_cast<size_t>(G.N) * sizeof(S);
   static_for<Q>([&](auto ii) {
     constexpr int i = ii;
-    Codec<S>::store(dst + static_cast<size_t>(i) * G.N + self, g[i]);
+    store_at<S>(cb + i * plane, self_bytes, g[i]);
   });
 }
 
@@ -130,8 +165,15 @@ struct Launch {
 };
 
 inline Launch node_launch(const Geo& G) {
-  int tx = 1;
-  while (tx < G.nx && tx < 256) tx *= 2;
+  // widest power-of-two row segment (<= 256) that divides nx, if nx is a multiple of 64;
+  // otherwise the smallest power of two covering nx (ragged rows, masked lanes)
+  int tx = 256;
+  if (G.nx % 64 == 0) {
+    while (G.nx % tx != 0) tx /= 2;
+  } else {
+    tx = 1;
+    while (tx < G.nx && tx < 256) tx *= 2;
+  }
   int ty = 256 / tx;
   int py = 1;
   while (py < G.ny) py *= 2;

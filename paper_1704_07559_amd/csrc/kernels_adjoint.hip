@@ -83,11 +83,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(Geo G, ModelF M, ForceF Fo
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
-  const unsigned self = nb.self;
+  const Nbr ne = neighbours(G, x, y, z);
+  const unsigned self = ne.self;
+  const Nbr nb = in_bytes<float>(ne);
 
   float lt[Q];
-  pull<LatRev>(lam_in, G, nb, y, lt);
+  pull<LatRev, float>(lam_in, G, nb, y, lt);
 
   // mu = D^-1 T lam~
   const Pairs P = make_pairs(lt);
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(Geo G, ModelF M, ForceF Fo
 
   float lo[Q];
   apply_transpose(nu, lo);
-  store_local<Q>(lam_out, G, self, lo);
+  store_local<Q>(lam_out, G, nb.self, lo);
 
   if (grad_force) {
     // G(j) = d S_F / d F
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ForceF 
     const Nbr nb = neighbours(G, x, y, z);
     const unsigned self = nb.self;
     float g[Q];
-    pull<LatFwd>(buf, G, nb, y, g);
+    pull<LatFwd, S>(buf, G, in_bytes<S>(nb), y, g);
     const Pairs P = make_pairs(g);
     const float drho = delta_rho(P);
     float Fx, Fy, Fz;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ForceF 
       constexpr int i = ii;
       lam[i] -= a + static_cast<float>(CX[i]) * bx + static_cast<float>(CY[i]) * by + static_cast<float>(CZ[i]) * bz;
     });
-    store_local<Q>(lam_out, G, self, lam);
+    store_local<Q>(lam_out, G, self * 4u, lam);
     if (grad_force) {
       grad_force[self] -= 0.5f * bx;
       grad_force[G.N + self] -= 0.5f * by;

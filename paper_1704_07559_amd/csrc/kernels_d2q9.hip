@@ -31,15 +31,16 @@ __device__ __forceinline__ void rates_with(const ModelF& M, float snu, float (&r
 
 __device__ __forceinline__ float strain_sq(const float (&S)[3]) { return S[0] * S[0] + S[1] * S[1] + 2.0f * S[2] * S[2]; }
 
-template <typename S>
+template <typename S, bool WALLS>
 __global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, 0);
-  const unsigned self = nb.self;
+  const Nbr ne = neighbours(G, x, y, 0);
+  const unsigned self = ne.self;
+  const Nbr nb = in_bytes<S>(ne);
   float g[Q];
-  pull<Lat>(static_cast<const S*>(io.src), G, nb, y, g);
+  pull<Lat, S, WALLS>(static_cast<const S*>(io.src), G, nb, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P);
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, For
     });
   }
   add_back_transform(dm, g);
-  store_local<Q>(static_cast<S*>(io.dst), G, self, g);
+  store_local<Q>(static_cast<S*>(io.dst), G, nb.self, g);
 }
 
 template <typename S>
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo,
   if (x >= G.nx || y >= G.ny) return;
   const Nbr nb = neighbours(G, x, y, 0);
   float g[Q];
-  pull<Lat>(buf, G, nb, y, g);
+  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float Fx, Fy;
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, floa
     mn[8] = -(dxy + dyx) / (3.0f * sn);
     add_back_transform(mn, g);
   }
-  scatter<Lat>(buf, G, nb, y, g);
+  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
   if (snu) snu[self] = M.s[7];
 }
 
@@ -160,8 +161,8 @@ __global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* ca
   if (x >= G.nx || y >= G.ny) return;
   const Nbr nb = neighbours(G, x, y, 0);
   float g[Q];
-  pull<Lat>(buf, G, nb, y, g);
-  store_local<Q>(canon, G, nb.self, g);
+  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  store_local<Q>(canon, G, nb.self * 4u, g);
 }
 
 template <typename S>
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void set_kernel(Geo G, S* buf, const float* ca
   float g[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = canon[static_cast<size_t>(i) * G.N + nb.self];
-  scatter<Lat>(buf, G, nb, y, g);
+  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
 }
 
 template <typename S>
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo,
     const int y = idx / G.nx;
     const Nbr nb = neighbours(G, x, y, 0);
     float g[Q];
-    pull<Lat>(buf, G, nb, y, g);
+    pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
     int bad = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);
@@ -215,13 +216,20 @@ static const S* cb(const void* p) {
   return static_cast<const S*>(p);
 }
 
+template <typename S>
+static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+                          const ForceF& Fo, const StepIO& io) {
+  if (walls) hipLaunchKernelGGL((step_kernel<S, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  else hipLaunchKernelGGL((step_kernel<S, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+}
+
 hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,
                        hipStream_t st) {
   const Launch L = node_launch(G);
   switch (storage) {
-    case 0: hipLaunchKernelGGL(step_kernel<float>, L.grid, L.block, 0, st, G, M, V, Fo, io); break;
-    case 1: hipLaunchKernelGGL(step_kernel<_Float16>, L.grid, L.block, 0, st, G, M, V, Fo, io); break;
-    case 2: hipLaunchKernelGGL(step_kernel<__bf16>, L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    case 0: launch_step_t<float>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    case 1: launch_step_t<_Float16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    case 2: launch_step_t<__bf16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -53,21 +53,12 @@ __device__ __forceinline__ float strain_sq(const float (&S)[6]) {
   return S[0] * S[0] + S[1] * S[1] + S[2] * S[2] + 2.0f * (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
 }
 
-// ------------------------------------------------------------------------------------------
-// The fused step
-// ------------------------------------------------------------------------------------------
-template <typename S>
-__global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
-  const unsigned self = nb.self;
-
-  float g[Q];
-  pull<Lat>(static_cast<const S*>(io.src), G, nb, y, g);
-
+// Everything one node does between the pull and the store: moments, strain of the incoming
+// state (Yu and/or Chai, with the lagged s_nu), viscosity model, relaxation with the Guo
+// term, back-transform. g holds the pulled pre-collision populations on entry and the
+// post-collision populations on exit; `self` is the node's element offset in the fields.
+__device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const Geo& G, const ModelF& M,
+                                            const ViscF& V, const ForceF& Fo, const StepIO& io) {
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P), jz = momentum<2>(P);
@@ -128,13 +119,29 @@ __global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, For
     });
   }
   add_back_transform(dm, g);
-  store_local<Q>(static_cast<S*>(io.dst), G, self, g);
 
   if (io.j_save) {
     io.j_save[self] = jx;
     io.j_save[G.N + self] = jy;
     io.j_save[2 * static_cast<size_t>(G.N) + self] = jz;
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// The fused step: one thread per node
+// ------------------------------------------------------------------------------------------
+template <typename S, bool WALLS>
+__global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr ne = neighbours(G, x, y, z);
+  const Nbr nb = in_bytes<S>(ne);
+  float g[Q];
+  pull<Lat, S, WALLS>(static_cast<const S*>(io.src), G, nb, y, g);
+  node_update(g, ne.self, G, M, V, Fo, io);
+  store_local<Q>(static_cast<S*>(io.dst), G, nb.self, g);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo,
   if (x >= G.nx || y >= G.ny) return;
   const Nbr nb = neighbours(G, x, y, z);
   float g[Q];
-  pull<Lat>(buf, G, nb, y, g);
+  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P), jz = momentum<2>(P);
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, floa
     mn[15] = -(d[2] + d[6]) / (3.0f * sn);
     add_neq_from_moments(mn, g);
   }
-  scatter<Lat>(buf, G, nb, y, g);
+  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
   if (snu) snu[self] = M.s[9];
 }
 
@@ -224,8 +231,8 @@ __global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* ca
   if (x >= G.nx || y >= G.ny) return;
   const Nbr nb = neighbours(G, x, y, z);
   float g[Q];
-  pull<Lat>(buf, G, nb, y, g);
-  store_local<Q>(canon, G, nb.self, g);
+  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  store_local<Q>(canon, G, nb.self * 4u, g);
 }
 
 template <typename S>
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(256) void set_kernel(Geo G, S* buf, const float* ca
   float g[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = canon[static_cast<size_t>(i) * G.N + nb.self];
-  scatter<Lat>(buf, G, nb, y, g);
+  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -256,7 +263,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo,
     const int z = t / G.ny;
     const Nbr nb = neighbours(G, x, y, z);
     float g[Q];
-    pull<Lat>(buf, G, nb, y, g);
+    pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
     int bad = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);
@@ -290,25 +297,27 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo,
 // ------------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------------
-#define LBM_DISPATCH_STORAGE(storage, KERNEL, GRID, BLOCK, STREAM, ...)                                 \
-  do {                                                                                                 \
-    switch (storage) {                                                                                 \
-      case 0: hipLaunchKernelGGL(KERNEL<float>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;           \
-      case 1: hipLaunchKernelGGL(KERNEL<_Float16>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;        \
-      case 2: hipLaunchKernelGGL(KERNEL<__bf16>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;          \
-      default: return hipErrorInvalidValue;                                                            \
-    }                                                                                                  \
-  } while (0)
-
 template <typename S>
 static const S* cbuf(const void* p) {
   return static_cast<const S*>(p);
 }
 
+template <typename S>
+static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+                          const ForceF& Fo, const StepIO& io) {
+  if (walls) hipLaunchKernelGGL((step_kernel<S, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  else hipLaunchKernelGGL((step_kernel<S, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+}
+
 hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,
                        hipStream_t st) {
   const Launch L = node_launch(G);
-  LBM_DISPATCH_STORAGE(storage, step_kernel, L.grid, L.block, st, G, M, V, Fo, io);
+  switch (storage) {
+    case 0: launch_step_t<float>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    case 1: launch_step_t<_Float16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    case 2: launch_step_t<__bf16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

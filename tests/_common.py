@@ -67,3 +67,47 @@ def strain_rel_err(S_gpu, S_ref):
 
 def to_np(t):
     return t.detach().cpu().numpy().astype(np.float64)
+
+
+def sample_nodes(shape, count, seed):
+    """Seeded node sample (z, y, x) including the eight corners of the box."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    nodes = {(z, y, x) for z in (0, nz - 1) for y in (0, ny - 1) for x in (0, nx - 1)}
+    while len(nodes) < count:
+        nodes.add((int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))))
+    return sorted(nodes)
+
+
+def patch_reference(make_params, u, node, k, walls, force=None):
+    """FP64 oracle values at one node after k steps, from the radius-k neighbourhood of the
+    initial field only (the value of a node after k steps depends on no other node).
+
+    Periodic axes wrap; with y-walls the rows are clipped at the walls and the patch streams
+    with bounce-back (a wrong edge at an interior cut cannot reach the centre in k steps).
+    Returns (g after k steps at the node, Yu strain of every step's pre-collision state at
+    the node, s_nu after k steps at the node)."""
+    from oracle import d3q19 as od
+    _, nz, ny, nx = u.shape
+    z, y, x = node
+    zs = [(z + d) % nz for d in range(-k, k + 1)]
+    xs = [(x + d) % nx for d in range(-k, k + 1)]
+    if walls:
+        ys = list(range(max(0, y - k), min(ny - 1, y + k) + 1))
+    else:
+        ys = [(y + d) % ny for d in range(-k, k + 1)]
+    ix = np.ix_(zs, ys, xs)
+    up = np.stack([u[c][ix] for c in range(3)])
+    Fp = None
+    if force is not None:
+        F = np.asarray(force)
+        Fp = F if F.shape == (3,) else np.stack([F[c][ix] for c in range(3)])
+    p = make_params(Fp)
+    pshape = up.shape[1:]
+    sim = od.Simulation(p, od.init_populations(np.zeros(pshape), up, p))
+    cz, cy, cx = k, ys.index(y), k
+    strains = []
+    for _ in range(k):
+        out = sim.step(1)
+        strains.append(out.S_yu[:, cz, cy, cx].copy())
+    return sim.g[:, cz, cy, cx].copy(), strains, float(sim.s_nu[cz, cy, cx])

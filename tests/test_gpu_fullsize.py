@@ -1,0 +1,95 @@
+"""Parity at the full sizes of the benchmarked configurations, in the launch configuration
+bench.py times, on sampled nodes whose FP64 oracle values are computed one by one from
+the node's neighbourhood (see _common.patch_reference), plus conservation properties of
+the whole field.
+
+* LES 256^3, FP32, Smagorinsky from the Yu strain (the headline workload);
+* power-law channel 128 x 128 x 512 with y-walls and a body force (Chai-driven viscosity);
+* LES 384^3 with FP16 storage (tolerance from the FP16 rounding of the stored deviation).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import d3q19 as od
+from tests._common import needs_gpu, patch_reference, sample_nodes, spec_params
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+K = 2  # steps compared node by node
+
+
+def _run(shape, u, storage, kw, force=None, nsample=40, seed=0):
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    op, cp, _ = spec_params(shape, storage=storage, force=force, **kw)
+    sim = lbm.LBM(cp, lbm.rho_u_field(np.zeros(shape), u))
+    S = [torch.empty((6,) + shape, device="cuda") for _ in range(K)]
+    for n in range(K):
+        sim.step(1, S_out=S[n], strain_kind=capi.LBM_STRAIN_YU)
+    g = sim.populations()
+    nodes = sample_nodes(shape, nsample, seed)
+    idx = tuple(torch.tensor(a, device="cuda") for a in zip(*nodes))
+    g_s = g[(slice(None),) + idx].double().cpu().numpy()          # (19, nsample)
+    S_s = [s[(slice(None),) + idx].double().cpu().numpy() for s in S]
+    snu_s = (sim.s_nu.reshape(shape)[idx].double().cpu().numpy() if sim.s_nu is not None else None)
+    diag = sim.reduce()
+    sim.close()
+
+    def make_params(Fp):
+        q = od.Params(**{f: getattr(op, f) for f in op.__dataclass_fields__})
+        q.force = Fp
+        return q
+
+    worst_g = worst_s = 0.0
+    dS, frob = 0.0, 0.0
+    wts = np.array([1, 1, 1, 2, 2, 2])
+    for m, node in enumerate(nodes):
+        g_ref, S_ref, snu_ref = patch_reference(make_params, u, node, K, op.walls_y, force)
+        f_ref = g_ref + od.W * op.rho0
+        worst_g = max(worst_g, float(np.max(np.abs(g_s[:, m] + od.W * op.rho0 - f_ref) / np.abs(f_ref))))
+        for n in range(K):
+            dS = max(dS, float(np.abs(S_s[n][:, m] - S_ref[n]).max()))
+            frob = max(frob, float(np.sqrt((wts * S_ref[n] ** 2).sum())))
+        if snu_s is not None:
+            worst_s = max(worst_s, abs(snu_s[m] - snu_ref) / snu_ref)
+    # strain error normalised by the largest strain norm among the sampled nodes
+    return worst_g, dS / frob, worst_s, diag
+
+
+@pytest.mark.slow
+def test_les_256_cubed_fp32_sampled():
+    shape = (256, 256, 256)
+    u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
+    kw = dict(tau=0.51, visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    wg, wS, ws, diag = _run(shape, u, "f32", kw)
+    assert wg < 1e-5 and wS < 1e-4 and ws < 1e-5, (wg, wS, ws)
+    assert diag["nonfinite"] == 0
+    assert abs(diag["mass"]) < 1e-6 * shape[0] ** 3        # started with delta_rho = 0
+    assert np.abs(diag["mom"]).max() < 1e-6 * np.abs(u).sum()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n_pl", [0.5, 1.5])
+def test_powerlaw_channel_128x128x512_sampled(n_pl):
+    shape = (512, 128, 128)  # (nz, ny, nx): walls in y, force along z
+    rng_u = synth.random_vector(shape, seed=3, scale=0.01)   # a perturbed start, so the strain is not zero
+    F = np.array([0.0, 0.0, 1e-6])
+    gref = 1e-6 * 128 / (2 * 0.1)
+    kw = dict(tau=0.8, visc="powerlaw", drive="chai", K_pl=0.1 * gref ** (1 - n_pl), n_pl=n_pl, nu_min=1e-3,
+              nu_max=1.0, walls=True)
+    wg, wS, ws, diag = _run(shape, rng_u, "f32", kw, force=F, seed=1)
+    assert wg < 1e-5 and wS < 1e-4 and ws < 1e-5, (wg, wS, ws)
+    assert diag["nonfinite"] == 0
+
+
+@pytest.mark.slow
+def test_les_384_cubed_fp16_sampled():
+    shape = (384, 384, 384)
+    u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
+    kw = dict(tau=0.51, visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    wg, wS, ws, diag = _run(shape, u, "f16", kw, nsample=24, seed=2)
+    # FP16 keeps 11 significant bits of the stored deviation g (|g| < 0.4 f): a few
+    # half-ulps per step on f
+    assert wg < 4 * 2.0 ** -11, wg
+    assert diag["nonfinite"] == 0
