@@ -7,27 +7,41 @@
 
 namespace lbm {
 
+// Population planes are streamed: every element is read once and written once per step,
+// so their loads and stores carry the nontemporal hint (load_cached is the plain load).
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void stream_store(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 template <typename S>
 struct Codec;
 
 template <>
 struct Codec<float> {
-  static __device__ __forceinline__ float load(const float* p) { return *p; }
-  static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+  static __device__ __forceinline__ float load_cached(const float* p) { return *p; }
+  static __device__ __forceinline__ float load(const float* p) { return stream_load(p); }
+  static __device__ __forceinline__ void store(float* p, float v) { stream_store(p, v); }
 };
 
 template <>
 struct Codec<_Float16> {
-  static __device__ __forceinline__ float load(const _Float16* p) { return static_cast<float>(*p); }
+  static __device__ __forceinline__ float load_cached(const _Float16* p) { return static_cast<float>(*p); }
+  static __device__ __forceinline__ float load(const _Float16* p) { return static_cast<float>(stream_load(p)); }
   // fptrunc float -> half rounds to nearest even (default rounding mode).
-  static __device__ __forceinline__ void store(_Float16* p, float v) { *p = static_cast<_Float16>(v); }
+  static __device__ __forceinline__ void store(_Float16* p, float v) { stream_store(p, static_cast<_Float16>(v)); }
 };
 
 template <>
 struct Codec<__bf16> {
-  static __device__ __forceinline__ float load(const __bf16* p) { return static_cast<float>(*p); }
+  static __device__ __forceinline__ float load_cached(const __bf16* p) { return static_cast<float>(*p); }
+  static __device__ __forceinline__ float load(const __bf16* p) { return static_cast<float>(stream_load(p)); }
   // fptrunc float -> bfloat rounds to nearest even.
-  static __device__ __forceinline__ void store(__bf16* p, float v) { *p = static_cast<__bf16>(v); }
+  static __device__ __forceinline__ void store(__bf16* p, float v) { stream_store(p, static_cast<__bf16>(v)); }
 };
 
 }  // namespace lbm

@@ -82,6 +82,10 @@ __device__ __forceinline__ float load_at(const void* base, unsigned byte_off) {
   return Codec<S>::load(reinterpret_cast<const S*>(static_cast<const char*>(base) + byte_off));
 }
 template <typename S>
+__device__ __forceinline__ float load_at_cached(const void* base, unsigned byte_off) {
+  return Codec<S>::load_cached(reinterpret_cast<const S*>(static_cast<const char*>(base) + byte_off));
+}
+template <typename S>
 __device__ __forceinline__ void store_at(void* base, unsigned byte_off, float v) {
   Codec<S>::store(reinterpret_cast<S*>(static_cast<char*>(base) + byte_off), v);
 }
@@ -99,7 +103,11 @@ __device__ __forceinline__ bool crosses_wall(const Geo& G, int y) {
 // population i of node x - c_i (periodic), or of population opp(i) at x across a wall.
 // nb holds byte offsets for S. With WALLS false the bounce test is compiled out and every
 // population plane is addressed from a wave-uniform base.
-template <class L, typename S, bool WALLS = true>
+// Cache policy: every population is read once per step, so loads are nontemporal, except
+// (ROW_BLOCKS false) the ten x-shifted populations when a block holds only part of an
+// x-row: their first or last cache line is also read by the neighbouring block, which
+// may run on another XCD, and a streaming hint there costs a refetch from HBM.
+template <class L, typename S, bool WALLS = true, bool ROW_BLOCKS = true>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, const Nbr& nb, int y, float (&g)[L::Q]) {
   const char* cb = reinterpret_cast<const char*>(src);
   const size_t plane = static_cast<size_t>(G.N) * sizeof(S);
@@ -112,7 +120,8 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, co
         return;
       }
     }
-    g[i] = load_at<S>(cb + i * plane, off);
+    if constexpr (L::cx(i) != 0 && !ROW_BLOCKS) g[i] = load_at_cached<S>(cb + i * plane, off);
+    else g[i] = load_at<S>(cb + i * plane, off);
   });
 }
 
@@ -158,15 +167,18 @@ __device__ __forceinline__ float viscous_rate(float SS, const ViscF& V) {
   return 1.0f / (3.0f * nu + 0.5f);
 }
 
-// Launch shape for the node-parallel kernels: one thread per node, 256-thread blocks of
-// (TX, TY) nodes with TX a power of two covering x, grid (ceil(nx/TX), ceil(ny/TY), nz).
+// Launch shape for the node-parallel kernels: one thread per node, blocks of (TX, TY)
+// nodes (at most kMaxBlock threads), grid (ceil(nx/TX), ceil(ny/TY), nz).
+constexpr int kMaxBlock = 256;
+
 struct Launch {
   dim3 grid, block;
 };
 
 inline Launch node_launch(const Geo& G) {
-  // widest power-of-two row segment (<= 256) that divides nx, if nx is a multiple of 64;
-  // otherwise the smallest power of two covering nx (ragged rows, masked lanes)
+  // 256-thread blocks (one wave per SIMD of a CU). The row segment tx is the widest power
+  // of two (<= 256) dividing nx when nx is a multiple of 64; ragged rows use the smallest
+  // power of two covering nx (masked lanes).
   int tx = 256;
   if (G.nx % 64 == 0) {
     while (G.nx % tx != 0) tx /= 2;

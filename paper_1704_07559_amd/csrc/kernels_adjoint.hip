@@ -76,7 +76,7 @@ __device__ __forceinline__ void force_at(const ForceF& Fo, unsigned N, unsigned 
   }
 }
 
-__global__ __launch_bounds__(256) void adjoint_kernel(Geo G, ModelF M, ForceF Fo, const float* __restrict__ j_n,
+__global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, ForceF Fo, const float* __restrict__ j_n,
                                                       const float* __restrict__ lam_in, float* __restrict__ lam_out,
                                                       float* __restrict__ grad_force) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ForceF 
 }
 
 // grad_u0 = sum_i lam0_i d g^eq_i / d u at (drho, u0): rho0 w_i (3 c_i + 9 (c_i.u) c_i - 3 u).
-__global__ __launch_bounds__(256) void init_adjoint_kernel(Geo G, ModelF M, const float* __restrict__ rho_u,
+__global__ __launch_bounds__(kMaxBlock) void init_adjoint_kernel(Geo G, ModelF M, const float* __restrict__ rho_u,
                                                            const float* __restrict__ lam0, float* __restrict__ grad_u0) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;

@@ -31,16 +31,17 @@ __device__ __forceinline__ void rates_with(const ModelF& M, float snu, float (&r
 
 __device__ __forceinline__ float strain_sq(const float (&S)[3]) { return S[0] * S[0] + S[1] * S[1] + 2.0f * S[2] * S[2]; }
 
-template <typename S, bool WALLS>
-__global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+template <typename S, bool WALLS, bool ROWS>
+__global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
   const Nbr ne = neighbours(G, x, y, 0);
   const unsigned self = ne.self;
   const Nbr nb = in_bytes<S>(ne);
   float g[Q];
-  pull<Lat, S, WALLS>(static_cast<const S*>(io.src), G, nb, y, g);
+  pull<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, nb, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P);
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, For
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
+__global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
                                                      int kind, float* S_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo,
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, float* snu, const float* rho_u,
+__global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf, float* snu, const float* rho_u,
                                                    const float* grad_u) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, floa
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* canon) {
+__global__ __launch_bounds__(kMaxBlock) void get_kernel(Geo G, const S* buf, float* canon) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= G.nx || y >= G.ny) return;
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* ca
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void set_kernel(Geo G, S* buf, const float* canon) {
+__global__ __launch_bounds__(kMaxBlock) void set_kernel(Geo G, S* buf, const float* canon) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= G.nx || y >= G.ny) return;
@@ -219,8 +220,15 @@ static const S* cb(const void* p) {
 template <typename S>
 static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const StepIO& io) {
-  if (walls) hipLaunchKernelGGL((step_kernel<S, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-  else hipLaunchKernelGGL((step_kernel<S, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  // whole x-rows per block: every load may stream (see pull)
+  const bool rows = static_cast<int>(L.block.x) >= G.nx;
+  if (walls) {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, true, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  } else {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, false, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  }
 }
 
 hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,

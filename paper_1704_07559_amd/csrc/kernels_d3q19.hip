@@ -130,8 +130,8 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
 // ------------------------------------------------------------------------------------------
 // The fused step: one thread per node
 // ------------------------------------------------------------------------------------------
-template <typename S, bool WALLS>
-__global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+template <typename S, bool WALLS, bool ROWS>
+__global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, For
   const Nbr ne = neighbours(G, x, y, z);
   const Nbr nb = in_bytes<S>(ne);
   float g[Q];
-  pull<Lat, S, WALLS>(static_cast<const S*>(io.src), G, nb, y, g);
+  pull<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, nb, y, g);
   node_update(g, ne.self, G, M, V, Fo, io);
   store_local<Q>(static_cast<S*>(io.dst), G, nb.self, g);
 }
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void step_kernel(Geo G, ModelF M, ViscF V, For
 // Strain of the current state (read only)
 // ------------------------------------------------------------------------------------------
 template <typename S>
-__global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
+__global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
                                                      int kind, float* S_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void strain_kernel(Geo G, ModelF M, ForceF Fo,
 // Initial state g^eq(delta_rho, rho0 u) [+ Chapman-Enskog non-equilibrium part]
 // ------------------------------------------------------------------------------------------
 template <typename S>
-__global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, float* snu, const float* rho_u,
+__global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf, float* snu, const float* rho_u,
                                                    const float* grad_u) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void init_kernel(Geo G, ModelF M, S* buf, floa
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* canon) {
+__global__ __launch_bounds__(kMaxBlock) void get_kernel(Geo G, const S* buf, float* canon) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void get_kernel(Geo G, const S* buf, float* ca
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void set_kernel(Geo G, S* buf, const float* canon) {
+__global__ __launch_bounds__(kMaxBlock) void set_kernel(Geo G, S* buf, const float* canon) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -305,8 +305,15 @@ static const S* cbuf(const void* p) {
 template <typename S>
 static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const StepIO& io) {
-  if (walls) hipLaunchKernelGGL((step_kernel<S, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-  else hipLaunchKernelGGL((step_kernel<S, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  // whole x-rows per block: every load may stream (see pull)
+  const bool rows = static_cast<int>(L.block.x) >= G.nx;
+  if (walls) {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, true, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  } else {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, false, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  }
 }
 
 hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,
