@@ -118,3 +118,54 @@ def test_checkpoint_interval_does_not_change_the_gradient():
         ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, 21, every)).backward()
         grads.append((u0_t.grad.clone(), F_t.grad.clone()))
     assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
+def test_strain_loss_gradient_500_steps_against_stored_oracle():
+    """The adjoint recipe at its full length on 16^3: 500 steps, checkpoint every 50, against
+    the FP64 oracle gradient stored by tests/golden/make_adjoint_golden.py."""
+    import pathlib
+
+    import torch
+    from paper_1704_07559_amd import autograd as ag
+    ref = np.load(pathlib.Path(__file__).parent / "golden" / "adjoint_c4_16cubed_500.npz")
+    shape, u0, F = _c4(16)
+    op, cp, _ = spec_params(shape, tau=0.8)
+    u0_t = torch.as_tensor(u0.astype(np.float32)).cuda().requires_grad_(True)
+    F_t = torch.as_tensor(F.astype(np.float32)).cuda().requires_grad_(True)
+    J = ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, int(ref["steps"]), int(ref["every"])))
+    J.backward()
+    assert abs(J.item() - float(ref["J"])) < 1e-4 * float(ref["J"])
+    assert _rel(to_np(u0_t.grad), ref["grad_u0"]) < 1e-4
+    assert _rel(to_np(F_t.grad), ref["grad_F"]) < 1e-4
+
+
+def test_gpu_gradient_against_gpu_finite_differences():
+    """Directional derivatives of the GPU loss (FP32 states, J accumulated in FP64) by the
+    five-point central difference, against the GPU adjoint gradient (16^3, 40 steps)."""
+    import torch
+    from paper_1704_07559_amd import autograd as ag
+    shape, u0, F = _c4(16)
+    op, cp, _ = spec_params(shape, tau=0.8)
+    prob = ag.StrainLossProblem(cp, 40, 10)
+    u0_t = torch.as_tensor(u0.astype(np.float32)).cuda().requires_grad_(True)
+    F_t = torch.as_tensor(F.astype(np.float32)).cuda().requires_grad_(True)
+    ag.strain_loss(u0_t, F_t, prob).backward()
+    du = torch.as_tensor(synth.random_vector(shape, seed=5, scale=1.0).astype(np.float32)).cuda()
+    dF = torch.as_tensor(synth.random_vector(shape, seed=6, scale=1.0).astype(np.float32)).cuda()
+
+    def J(u, f):
+        with torch.no_grad():
+            return ag.strain_loss(u, f, prob).item()
+
+    def fd5(fun, h):
+        return (8 * (fun(h) - fun(-h)) - (fun(2 * h) - fun(-2 * h))) / (12 * h)
+
+    u_d, F_d = u0_t.detach(), F_t.detach()
+    hu = 1e-3 * float(u_d.abs().max())
+    hF = 1e-5  # |F| ~ 1e-6: a larger step keeps the FP32 rounding of J far below the signal
+    fd_u = fd5(lambda t: J(u_d + t * du, F_d), hu)
+    fd_F = fd5(lambda t: J(u_d, F_d + t * dF), hF)
+    ad_u = float((u0_t.grad.double() * du.double()).sum())
+    ad_F = float((F_t.grad.double() * dF.double()).sum())
+    assert abs(fd_u - ad_u) < 1e-3 * abs(ad_u), (fd_u, ad_u)
+    assert abs(fd_F - ad_F) < 1e-3 * abs(ad_F), (fd_F, ad_F)

@@ -175,3 +175,43 @@ def test_reduce_is_deterministic_and_conserves():
     scale_m = np.abs(dr).sum()
     assert abs(d1["mass"] - d0["mass"]) < 1e-5 * scale_m
     assert np.abs(d1["mom"] - d0["mom"]).max() < 1e-5 * np.abs(u).sum()
+
+
+def test_error_paths_return_status_without_launching():
+    """Unsupported or invalid calls on a live context return a status and leave the state
+    untouched (no launch happens)."""
+    import torch
+    capi, lbm = _lib()
+    shape = (4, 6, 64)
+    op, cp, _ = spec_params(shape, visc="smagorinsky", nu0=0.01)
+    sim = lbm.LBM(cp)
+    before = sim.populations().clone()
+    N = cp.N
+    lam = torch.zeros((19, N), device="cuda")
+    for call, status in (
+        (lambda: capi.lbm_adjoint_step(sim.ctx, torch.zeros((3, N), device="cuda"), lam, torch.empty_like(lam)),
+         capi.LBM_EUNSUPPORTED),                                   # variable viscosity
+        (lambda: capi.lbm_strain_loss_seed(sim.ctx, lam), capi.LBM_EUNSUPPORTED),
+        (lambda: capi.lbm_step(sim.ctx, -1), capi.LBM_EINVAL),
+        (lambda: capi.lbm_step(sim.ctx, 1, torch.empty((6, N), device="cuda"), 7), capi.LBM_EINVAL),
+        (lambda: capi.lbm_strain(sim.ctx, capi.LBM_STRAIN_YU, None), capi.LBM_EINVAL),
+    ):
+        with pytest.raises(capi.LBMError) as e:
+            call()
+        assert e.value.status == status, capi.lbm_last_error()
+    sim.step(0)
+    assert torch.equal(sim.populations(), before)
+    assert sim.step_count == 0
+
+
+def test_adjoint_lam_aliasing_rejected():
+    import torch
+    capi, lbm = _lib()
+    shape = (4, 6, 64)
+    op, cp, _ = spec_params(shape)
+    sim = lbm.LBM(cp)
+    N = cp.N
+    lam = torch.zeros((19, N), device="cuda")
+    with pytest.raises(capi.LBMError) as e:
+        capi.lbm_adjoint_step(sim.ctx, torch.zeros((3, N), device="cuda"), lam, lam)
+    assert e.value.status == capi.LBM_EINVAL
