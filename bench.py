@@ -323,6 +323,20 @@ def main():
                                        "ke": d3["ke"], "nonfinite": d3["nonfinite"]}
         del rho_u3
         torch.cuda.empty_cache()
+        # the same 256^3 LES with the implicit (non-lagged) Smagorinsky coupling: no s_nu field
+        pi = les_params(capi, n, capi.LBM_F32)
+        pi.visc_kind = capi.LBM_VISC_SMAGORINSKY_IMPLICIT
+        si = lbm.LBM(pi, lbm.rho_u_field(np.zeros((n, n, n)), u))
+        log(f"FP32 {n}^3 implicit Smagorinsky: {args.warmup} warmup + {args.steps} timed steps")
+        wi, ki, di = time_run(si, args.steps, args.warmup)
+        si.close()
+        del si
+        torch.cuda.empty_cache()
+        extra["les256_implicit_smagorinsky"] = {"MLUPS": round(N * args.steps / wi / 1e6, 1),
+                                                "ms_per_step": round(wi / args.steps * 1e3, 4),
+                                                "kernel_ms": round(ki * 1e3, 4), "bytes_per_node": 152,
+                                                "hbm_frac": round(152 * N / ki / 1e9 / HBM_PEAK_GBS, 4),
+                                                "ke": di["ke"], "nonfinite": di["nonfinite"]}
         result["extra"] = extra
 
     if not args.no_extra:

@@ -57,7 +57,12 @@ typedef enum {
 typedef enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 } lbm_lattice;
 typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
 typedef enum { LBM_STRAIN_NONE = 0, LBM_STRAIN_YU = 1, LBM_STRAIN_CHAI = 2 } lbm_strain_kind;
-typedef enum { LBM_VISC_CONST = 0, LBM_VISC_SMAGORINSKY = 1, LBM_VISC_POWERLAW = 2 } lbm_visc_kind;
+typedef enum {
+  LBM_VISC_CONST = 0,
+  LBM_VISC_SMAGORINSKY = 1,
+  LBM_VISC_POWERLAW = 2,
+  LBM_VISC_SMAGORINSKY_IMPLICIT = 3
+} lbm_visc_kind;
 
 /*
  * Model parameters.
@@ -71,6 +76,9 @@ typedef enum { LBM_VISC_CONST = 0, LBM_VISC_SMAGORINSKY = 1, LBM_VISC_POWERLAW =
  *             nu = nu_max (n_pl < 1) or nu_min (n_pl > 1) at |S| = 0. |S| = sqrt(2 S:S).
  *             s_nu = 1/(3 nu + 1/2) relaxes the collision; the strain of the next step
  *             uses the s_nu of the previous collision at the node (held in s_nu_field).
+ *             LBM_VISC_SMAGORINSKY_IMPLICIT (D3Q19): no lagged field; every node solves
+ *             s_nu = 1/(3 (nu0 + c_smag^2 |S(s_nu)|) + 1/2), S(s_nu) being the strain formula
+ *             (affine in s_nu) at the rate of this very collision; s_nu_field may be NULL.
  *  visc_strain which formula drives the viscosity (LBM_STRAIN_YU or LBM_STRAIN_CHAI).
  *  walls_y    0: periodic in y. 1: halfway bounce-back walls at y = -1/2 and y = ny - 1/2.
  *  force[3]   uniform body force (Guo forcing, j = sum c g + F/2) used when
@@ -98,8 +106,8 @@ size_t lbm_population_bytes(const lbm_params* p);
 /*
  * Create a context over caller-owned device buffers and write the initial state.
  *  f_a, f_b     two distinct population buffers of lbm_population_bytes(p) bytes.
- *  s_nu_field   device float[N]; required unless visc_kind == LBM_VISC_CONST (may be NULL
- *               then). Filled with the initial s_nu.
+ *  s_nu_field   device float[N]; required for LBM_VISC_SMAGORINSKY and LBM_VISC_POWERLAW
+ *               (may be NULL otherwise). Filled with the initial s_nu.
  *  rho_u        device float[4*N]: planes delta_rho, u_x, u_y, u_z (u_z ignored for D2Q9);
  *               NULL = fluid at rest. Initial populations are g^eq(delta_rho, rho0 u)
  *               (the delta-rho form of Eq. edf).

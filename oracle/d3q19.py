@@ -19,7 +19,8 @@ repository's design notes):
   uses the commonly quoted d'Humieres set and s_c = 0 (Section 2 says the conserved rates
   are set to zero).
 * With a variable viscosity the strain at step n is evaluated with the s_nu of the previous
-  collision at the same node (lagged), held in an explicit field.
+  collision at the same node (lagged), held in an explicit field; the
+  "smagorinsky_implicit" model instead solves the local coupling s_nu(S(s_nu)) per node.
 * Body force: Guo forcing written in moment space, with j = sum c g + F/2.
 """
 from __future__ import annotations
@@ -105,7 +106,7 @@ class Params:
     omega_eps: float = 3.0       # Eq. meq
     omega_epsj: float = -5.5     # Eq. meq
     omega_xx: float = -0.5       # Eq. meq
-    visc_kind: str = "const"     # "const" | "smagorinsky" | "powerlaw"
+    visc_kind: str = "const"     # "const" | "smagorinsky" | "powerlaw" | "smagorinsky_implicit"
     visc_strain: str = "yu"      # which formula drives the viscosity: "yu" | "chai"
     nu0: float = 0.0             # Smagorinsky molecular viscosity
     c_smag: float = 0.1          # Smagorinsky constant, filter width Delta = 1
@@ -287,6 +288,25 @@ def viscosity_rate(S: np.ndarray, p: Params, s_nu_const: float) -> np.ndarray:
     return 1.0 / (3.0 * nu + 0.5)
 
 
+def implicit_smagorinsky_rate(S_of_s, p: Params, shape) -> np.ndarray:
+    """s_nu solving s = 1 / (3 (nu0 + C_s^2 |S(s)|) + 1/2) at every node, where S(s) is the
+    strain formula evaluated with s_nu = s (both formulas are affine in s_nu).
+
+    The s_e part of S is isotropic and the s_nu part traceless, so |S(s)|^2 = |P|^2 + s^2 |A|^2
+    and f(s) = s (3 nu(s) + 1/2) - 1 is increasing on [0, 2], with f(0) = -1 and f(2) >= 0:
+    the root is unique; plain bisection to FP64 resolution.
+    """
+    lo = np.zeros(shape)
+    hi = np.full(shape, 2.0)
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        nu = p.nu0 + p.c_smag**2 * strain_norm(S_of_s(mid))
+        f = mid * (3.0 * nu + 0.5) - 1.0
+        lo = np.where(f < 0.0, mid, lo)
+        hi = np.where(f < 0.0, hi, mid)
+    return 0.5 * (lo + hi)
+
+
 # ---------------------------------------------------------------------------------------
 # Collision, streaming, the step (Eqs. mrteq, mrteqvT)
 # ---------------------------------------------------------------------------------------
@@ -321,11 +341,23 @@ def collide(g: np.ndarray, p: Params, s_nu_prev: np.ndarray) -> CollideOut:
     drho, j = macroscopic(g, F)
     m = moments(g)
     meq = m_eq(drho, j, p.rho0, p.omega_eps, p.omega_epsj, p.omega_xx)
-    s_prev = rates_field(p, s_nu_prev)
-    S_yu = strain_yu(m - meq, s_prev[1], s_prev[9], p.rho0)
-    S_chai = strain_chai(g - g_eq(drho, j, p.rho0), s_prev, p.rho0)
-    S_drive = S_yu if p.visc_strain == "yu" else S_chai
-    s_nu = viscosity_rate(S_drive, p, float(p.s[9]))
+    f_neq = g - g_eq(drho, j, p.rho0)
+    if p.visc_kind == "smagorinsky_implicit":
+        # non-lagged coupling: the strain uses the rate of this very collision
+        def yu_of(sv):
+            return strain_yu(m - meq, float(p.s[1]), sv, p.rho0)
+
+        def chai_of(sv):
+            return strain_chai(f_neq, rates_field(p, sv), p.rho0)
+
+        s_nu = implicit_smagorinsky_rate(yu_of if p.visc_strain == "yu" else chai_of, p, shape)
+        S_yu, S_chai = yu_of(s_nu), chai_of(s_nu)
+    else:
+        s_prev = rates_field(p, s_nu_prev)
+        S_yu = strain_yu(m - meq, s_prev[1], s_prev[9], p.rho0)
+        S_chai = strain_chai(f_neq, s_prev, p.rho0)
+        S_drive = S_yu if p.visc_strain == "yu" else S_chai
+        s_nu = viscosity_rate(S_drive, p, float(p.s[9]))
     s = rates_field(p, s_nu)
     SF = moments(guo_force_populations(j, F, p.rho0))
     m_post = m - s * (m - meq) + (1.0 - 0.5 * s) * SF
@@ -355,7 +387,11 @@ def stream(g_post: np.ndarray, walls_y: bool = False) -> np.ndarray:
 
 
 def strain_of_state(g: np.ndarray, p: Params, s_nu: np.ndarray, kind: str = "yu") -> np.ndarray:
-    """Strain of a pre-collision state g(x, n) with the rates in ``s_nu`` (Yu or Chai)."""
+    """Strain of a pre-collision state g(x, n) with the rates in ``s_nu`` (Yu or Chai); with
+    the implicit Smagorinsky coupling the rate is solved from the state itself."""
+    if p.visc_kind == "smagorinsky_implicit":
+        out = collide(g, p, s_nu)
+        return out.S_yu if kind == "yu" else out.S_chai
     F = p.force_field(g.shape[1:])
     drho, j = macroscopic(g, F)
     s = rates_field(p, s_nu)

@@ -27,7 +27,7 @@ LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOMEM, LBM_ESTATE, LBM_ENONFINITE, LBM_EUNSUP
 LBM_D2Q9, LBM_D3Q19 = 9, 19
 LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
 LBM_STRAIN_NONE, LBM_STRAIN_YU, LBM_STRAIN_CHAI = 0, 1, 2
-LBM_VISC_CONST, LBM_VISC_SMAGORINSKY, LBM_VISC_POWERLAW = 0, 1, 2
+LBM_VISC_CONST, LBM_VISC_SMAGORINSKY, LBM_VISC_POWERLAW, LBM_VISC_SMAGORINSKY_IMPLICIT = 0, 1, 2, 3
 
 EXPORTED = (
     "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_strain", "lbm_reduce", "lbm_get_populations",

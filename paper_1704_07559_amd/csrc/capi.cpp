@@ -79,10 +79,14 @@ lbm_status check_params(const lbm_params* p, int* Q, size_t* N) {
   }
   const int snu_slot = (q == 19) ? 9 : 7;
   if (!(p->s[snu_slot] > 0.0)) return fail(LBM_EINVAL, "s_nu must be positive");
-  if (p->visc_kind < LBM_VISC_CONST || p->visc_kind > LBM_VISC_POWERLAW) return fail(LBM_EINVAL, "bad visc_kind");
+  if (p->visc_kind < LBM_VISC_CONST || p->visc_kind > LBM_VISC_SMAGORINSKY_IMPLICIT)
+    return fail(LBM_EINVAL, "bad visc_kind");
+  if (p->visc_kind == LBM_VISC_SMAGORINSKY_IMPLICIT && q != 19)
+    return fail(LBM_EUNSUPPORTED, "the implicit Smagorinsky coupling is provided for D3Q19");
   if (p->visc_kind != LBM_VISC_CONST && p->visc_strain != LBM_STRAIN_YU && p->visc_strain != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "visc_strain must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
-  if (p->visc_kind == LBM_VISC_SMAGORINSKY && !(p->nu0 >= 0.0)) return fail(LBM_EINVAL, "nu0 must be >= 0");
+  if ((p->visc_kind == LBM_VISC_SMAGORINSKY || p->visc_kind == LBM_VISC_SMAGORINSKY_IMPLICIT) && !(p->nu0 >= 0.0))
+    return fail(LBM_EINVAL, "nu0 must be >= 0");
   if (p->visc_kind == LBM_VISC_POWERLAW &&
       !(p->K_pl > 0.0 && p->nu_min > 0.0 && p->nu_max >= p->nu_min && std::isfinite(p->n_pl)))
     return fail(LBM_EINVAL, "power law needs K_pl > 0 and 0 < nu_min <= nu_max");
@@ -165,7 +169,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
     const uintptr_t a = reinterpret_cast<uintptr_t>(f_a), b = reinterpret_cast<uintptr_t>(f_b);
     if ((a < b ? b - a : a - b) < bytes) return fail(LBM_EINVAL, "population buffers overlap");
   }
-  if (p->visc_kind != LBM_VISC_CONST && (st = check_field(s_nu_field, "s_nu_field")) != LBM_OK) return st;
+  const bool lagged = p->visc_kind == LBM_VISC_SMAGORINSKY || p->visc_kind == LBM_VISC_POWERLAW;
+  if (lagged && (st = check_field(s_nu_field, "s_nu_field")) != LBM_OK) return st;
   if (s_nu_field && !aligned(s_nu_field, 4)) return fail(LBM_EINVAL, "s_nu_field must be 4-byte aligned");
   if (rho_u && !aligned(rho_u, 4)) return fail(LBM_EINVAL, "rho_u must be 4-byte aligned");
   if (grad_u && !aligned(grad_u, 4)) return fail(LBM_EINVAL, "grad_u must be 4-byte aligned");
@@ -179,7 +184,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
   c->buf[0] = f_a;
   c->buf[1] = f_b;
   c->cur = 0;
-  c->snu = (p->visc_kind != LBM_VISC_CONST) ? s_nu_field : nullptr;
+  c->snu = lagged ? s_nu_field : nullptr;
   c->step = 0;
   fill_model(c);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&c->scratch), sizeof(double) * (kReduceBlocks + 1) * kReduceVals);
@@ -234,7 +239,7 @@ lbm_status lbm_strain(lbm_ctx* c, int strain_kind, float* S_out, void* stream) {
   if (strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
   const hipStream_t s = as_stream(stream);
-  hipError_t e = is3d(c) ? d3q19::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s)
+  hipError_t e = is3d(c) ? d3q19::launch_strain(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s)
                          : d2q9::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_strain");
 }
@@ -246,7 +251,7 @@ lbm_status lbm_reduce(lbm_ctx* c, double* host_out, void* stream) {
   const hipStream_t s = as_stream(stream);
   double* partials = c->scratch;
   double* dout = c->scratch + static_cast<size_t>(kReduceBlocks) * kReduceVals;
-  hipError_t e = is3d(c) ? d3q19::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s)
+  hipError_t e = is3d(c) ? d3q19::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s)
                          : d2q9::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s);
   if (e != hipSuccess) return hip_fail(e, "lbm_reduce");
   e = hipMemcpyAsync(host_out, dout, sizeof(double) * kReduceVals, hipMemcpyDeviceToHost, s);

@@ -24,7 +24,7 @@ struct ModelF {
 };
 
 struct ViscF {
-  int kind;        // 0 const, 1 Smagorinsky, 2 power law
+  int kind;        // 0 const, 1 Smagorinsky (lagged), 2 power law (lagged), 3 Smagorinsky (implicit)
   int drive_chai;  // 1: the Chai strain drives the viscosity, 0: the Yu strain
   float nu0, csmag2, Kpl, npl, numin, numax;
 };
@@ -216,12 +216,12 @@ hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float*
                        const float* grad_u, hipStream_t);
 hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
                        hipStream_t);
-hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
-                         int kind, float* S_out, hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, int kind, float* S_out, hipStream_t);
 hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
 hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
-hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
-                         double* partials, double* out, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, double* partials, double* out, hipStream_t);
 hipError_t launch_adjoint_step(const Geo&, const ModelF&, const ForceF&, const float* j_n, const float* lam_in,
                                float* lam_out, float* grad_force, hipStream_t);
 hipError_t launch_loss_seed(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, float* lam_out,

@@ -43,7 +43,7 @@ class LBM:
         self.f_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.f_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.s_nu = (torch.empty(params.N, dtype=torch.float32, device=self.device)
-                     if params.visc_kind != capi.LBM_VISC_CONST else None)
+                     if params.visc_kind in (capi.LBM_VISC_SMAGORINSKY, capi.LBM_VISC_POWERLAW) else None)
         self._force_ref = params.force_field
         self.ctx = capi.lbm_init(params, self.f_a, self.f_b, self.s_nu, rho_u, grad_u)
 

@@ -28,7 +28,8 @@ def spec_params(shape, tau=0.8, rho0=1.0, s=None, visc="const", drive="yu", wall
     from paper_1704_07559_amd import capi
     nz, ny, nx = shape
     sv = od.default_rates(tau) if s is None else np.asarray(s, dtype=np.float64)
-    vk = {"const": capi.LBM_VISC_CONST, "smagorinsky": capi.LBM_VISC_SMAGORINSKY, "powerlaw": capi.LBM_VISC_POWERLAW}[visc]
+    vk = {"const": capi.LBM_VISC_CONST, "smagorinsky": capi.LBM_VISC_SMAGORINSKY, "powerlaw": capi.LBM_VISC_POWERLAW,
+          "smagorinsky_implicit": capi.LBM_VISC_SMAGORINSKY_IMPLICIT}[visc]
     dk = {"yu": capi.LBM_STRAIN_YU, "chai": capi.LBM_STRAIN_CHAI}[drive]
     st = {"f32": capi.LBM_F32, "f16": capi.LBM_F16, "bf16": capi.LBM_BF16}[storage]
     op = od.Params(rho0=rho0, s=sv.copy(), omega_eps=omegas[0], omega_epsj=omegas[1], omega_xx=omegas[2],

@@ -70,6 +70,16 @@ def test_les_256_cubed_fp32_sampled():
 
 
 @pytest.mark.slow
+def test_les_256_cubed_fp32_implicit_smagorinsky_sampled():
+    shape = (256, 256, 256)
+    u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
+    kw = dict(tau=0.51, visc="smagorinsky_implicit", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    wg, wS, ws, diag = _run(shape, u, "f32", kw, seed=4)
+    assert wg < 1e-5 and wS < 1e-4, (wg, wS)
+    assert diag["nonfinite"] == 0
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("n_pl", [0.5, 1.5])
 def test_powerlaw_channel_128x128x512_sampled(n_pl):
     shape = (512, 128, 128)  # (nz, ny, nx): walls in y, force along z

@@ -388,3 +388,57 @@ def test_powerlaw_poiseuille_steady(n_pl):
     eta = np.arange(H) + 0.5
     ref = cf.powerlaw_poiseuille(eta, H, F, K, n_pl)
     assert np.abs(uz - ref).max() < 0.03 * ref.max()
+
+
+# --- implicit (non-lagged) Smagorinsky coupling -------------------------------------------
+
+def test_implicit_smagorinsky_rate_is_a_fixed_point():
+    """The solved s_nu satisfies s = 1/(3 (nu0 + C^2 |S(s)|) + 1/2) at every node to FP64
+    resolution, with S(s) recomputed independently from the reported strain, and both formulas
+    report the same strain (Section 5.1 identity at the solved rate)."""
+    shape = (3, 5, 7)
+    for drive in ("yu", "chai"):
+        p = d.Params(visc_kind="smagorinsky_implicit", visc_strain=drive, nu0=0.002, c_smag=0.3)
+        g = synth.random_state(19, shape, seed=31, scale=0.02)
+        out = d.collide(g, p, np.full(shape, p.s[9]))
+        S = out.S_yu if drive == "yu" else out.S_chai
+        lhs = out.s_nu * (3.0 * (p.nu0 + p.c_smag**2 * d.strain_norm(S)) + 0.5)
+        assert np.abs(lhs - 1.0).max() < 1e-14
+        assert np.abs(out.S_yu - out.S_chai).max() <= 1e-13 * np.abs(out.S_yu).max()
+        # the strain is the formula at the solved rate: rebuild it from the moments
+        drho, j = d.macroscopic(g)
+        mneq = d.moments(g) - d.m_eq(drho, j, p.rho0)
+        assert np.abs(d.strain_yu(mneq, p.s[1], out.s_nu, p.rho0) - out.S_yu).max() < 1e-16
+        # without an eddy viscosity the molecular rate is recovered
+        p0 = d.Params(visc_kind="smagorinsky_implicit", visc_strain=drive, nu0=0.1, c_smag=0.0)
+        assert np.abs(d.collide(g, p0, np.full(shape, p.s[9])).s_nu - 1.0 / 0.8).max() < 1e-14
+
+
+def test_implicit_smagorinsky_conserves():
+    shape = (4, 6, 5)
+    p = d.Params(visc_kind="smagorinsky_implicit", nu0=0.01, c_smag=0.2)
+    sim = d.Simulation(p, _smooth_state(shape, 3, p))
+    d0 = sim.diagnostics()
+    sim.step(20)
+    d1 = sim.diagnostics()
+    assert abs(d1["mass"] - d0["mass"]) < 1e-13
+    assert np.abs(d1["mom"] - d0["mom"]).max() < 1e-13
+
+
+def test_strain_splits_into_isotropic_bulk_and_traceless_shear_parts():
+    """S(s_nu) = P + s_nu A with P = (s_e part) a multiple of the identity and A traceless,
+    which makes |S(s)| increasing in s and the implicit root unique (Eq. LuoS)."""
+    shape = (3, 4, 5)
+    p = d.Params()
+    g = synth.random_state(19, shape, seed=32, scale=0.02)
+    drho, j = d.macroscopic(g)
+    mneq = d.moments(g) - d.m_eq(drho, j, p.rho0)
+    P = d.strain_yu(mneq, p.s[1], 0.0, p.rho0)
+    A = d.strain_yu(mneq, 0.0, 1.0, p.rho0)
+    scale = np.abs(A).max()
+    assert np.abs(P[3:]).max() < 1e-15 * scale
+    assert np.abs(P[0] - P[1]).max() < 1e-15 * scale and np.abs(P[0] - P[2]).max() < 1e-15 * scale
+    assert np.abs(A[0] + A[1] + A[2]).max() < 1e-15 * scale
+    assert np.abs(P).max() > 1e-3 * scale and np.abs(A[3:]).max() > 1e-3 * scale
+    s = 1.3
+    assert np.abs(d.strain_yu(mneq, p.s[1], s, p.rho0) - (P + s * A)).max() < 1e-15 * scale
