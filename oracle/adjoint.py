@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY. The paper has no adjoint; this is the exact transpose of the
 oracle's own forward step (``d3q19.collide`` + ``d3q19.stream``) for a constant viscosity,
-used to check the hand-written adjoint kernel.
+used to check the hand-written adjoint kernel (strain-dependent viscosities:
+``adjoint_visc``).
 
 Forward problem (all FP64):
   g^0      = g^eq(0, rho0 u0)                         (delta-rho form of Eq. edf)
@@ -86,17 +87,19 @@ def yu_map(p: d.Params, s_nu: float) -> np.ndarray:
 # Per-node Jacobians of the collision (Eq. mrteqvT with the Guo term)
 # ---------------------------------------------------------------------------------------
 
-def collision_jacobians(g: np.ndarray, F: np.ndarray, p: d.Params):
-    """Per-node dg*/dg (M, 19, 19) and dg*/dF (M, 19, 3) of the collision at state g.
+def collision_jacobians(g: np.ndarray, F: np.ndarray, p: d.Params, rates: np.ndarray | None = None):
+    """Per-node dg*/dg (M, 19, 19) and dg*/dF (M, 19, 3) of the collision at state g, with
+    the relaxation rates held fixed.
 
     With m = T g, delta_rho = sum g, j = C g + F/2 and
       m* = m - L (m - m^eq(delta_rho, j)) + (I - L/2) T F-bar(j, F),  g* = T^-1 m*,
       dm*/dg = (I - L) T + L dm^eq/dg + (I - L/2) T dF-bar/dj C
       dm*/dF = L dm^eq/dj / 2 + (I - L/2) T (dF-bar/dF + dF-bar/dj / 2)
-    with L = diag(s) (constant viscosity); diagonal products are written as broadcasts.
+    with L = diag(s): the rates of p (constant viscosity), or ``rates`` (19, M) per node;
+    diagonal products are written as broadcasts.
     """
-    if p.visc_kind != "const":
-        raise ValueError("the adjoint oracle covers a constant viscosity")
+    if rates is None and p.visc_kind != "const":
+        raise ValueError("a strain-dependent viscosity needs the per-node rates")
     q, *shape = g.shape
     M = int(np.prod(shape))
     gf = g.reshape(Q, M)
@@ -110,8 +113,8 @@ def collision_jacobians(g: np.ndarray, F: np.ndarray, p: d.Params):
     # dm^eq/dg = dm^eq/d(drho) 1^T + dm^eq/dj C            -> (M, 19, 19)
     dmeq_dg = dmr[None, :, None] * np.ones((1, 1, Q)) + np.einsum("rkm,ki->mri", dmj, Cf, optimize=True)
     TdfjC = np.einsum("ri,ikm,kl->mrl", d.T, dfj, Cf, optimize=True)      # T dF-bar/dj C
-    sv = p.s[None, :, None]                                               # L = diag(s)
-    dmstar_dg = ((np.eye(Q) - np.diag(p.s)) @ d.T)[None] + sv * dmeq_dg + (1.0 - sv / 2.0) * TdfjC
+    sv = p.s[None, :, None] if rates is None else rates.T[:, :, None]     # L = diag(s)
+    dmstar_dg = (1.0 - sv) * d.T[None] + sv * dmeq_dg + (1.0 - sv / 2.0) * TdfjC
     Jgg = np.matmul(d.TINV[None], dmstar_dg)
     TdfF = np.einsum("ri,ikm->mrk", d.T, dfF + dfj / 2.0, optimize=True)
     dmstar_dF = sv * np.transpose(dmj, (2, 0, 1)) / 2.0 + (1.0 - sv / 2.0) * TdfF
@@ -213,15 +216,22 @@ def init_adjoint(lam0: np.ndarray, u0: np.ndarray, p: d.Params) -> np.ndarray:
 # ---------------------------------------------------------------------------------------
 
 def forward(u0: np.ndarray, F: np.ndarray, p: d.Params, nsteps: int) -> float:
+    """J after nsteps; with a strain-dependent viscosity the strain of the final state takes
+    the rate the model gives it (the lagged field, or the implicitly solved rate)."""
     pf = _with_force(p, F)
     sim = d.Simulation(pf, d.init_populations(np.zeros(u0.shape[1:]), u0, pf))
     sim.step(nsteps)
-    return strain_loss(sim.g, F, p)
+    if p.visc_kind == "const":
+        return strain_loss(sim.g, F, p)
+    return float(d.strain_sq(sim.strain("yu")).sum())
 
 
 def gradient(u0: np.ndarray, F: np.ndarray, p: d.Params, nsteps: int, every: int | None = None):
     """(J, dJ/du0, dJ/dF) by the discrete adjoint. States are checkpointed every ``every``
     steps in the forward sweep and recomputed segment by segment in the reverse sweep."""
+    if p.visc_kind != "const":
+        from .adjoint_visc import gradient_visc
+        return gradient_visc(u0, F, p, nsteps, every)
     every = every or nsteps
     pf = _with_force(p, F)
     sim = d.Simulation(pf, d.init_populations(np.zeros(u0.shape[1:]), u0, pf))
