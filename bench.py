@@ -146,17 +146,24 @@ def copy_bandwidth(torch):
     return round(2 * (1 << 30) / t / 1e9, 1)
 
 
-def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50):
+def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50, visc="const"):
     """Strain-squared loss gradient on the 128^3 recipe (seeded spectrum velocity, uniform
     random force U(-1e-6, 1e-6), tau_nu = 0.8, 500 steps, checkpoint every 50): wall time of
     the forward pass and of the backward pass (recompute + adjoint), and the adjoint kernel
-    alone against HBM (algorithmic 200 B/node: 76 lambda in, 76 out, 12 j, 12 F, 24 grad_F)."""
+    alone against HBM. Algorithmic bytes per node of the adjoint kernel: 200 for a constant
+    viscosity (76 lambda in, 76 out, 12 j, 12 F, 24 grad_F); with visc="smagorinsky" (lagged,
+    C_s = 0.1 on top of nu0 = 0.1) 236 (+ 28 for the 7 extra record planes, + 8 for the
+    s_nu-field adjoint in and out)."""
     from paper_1704_07559_amd import autograd as ag
     shape = (n, n, n)
-    log(f"adjoint {n}^3: {nsteps} steps, checkpoint every {every}")
+    log(f"adjoint {n}^3 ({visc}): {nsteps} steps, checkpoint every {every}")
     u0 = torch.as_tensor(synth.spectrum_velocity(shape, seed=1704, u_rms=0.04).astype(np.float32)).cuda()
     F = torch.as_tensor(synth.uniform_random_force(shape, seed=7559, amp=1e-6).astype(np.float32)).cuda()
     p = capi.Params(nx=n, ny=n, nz=n, s=rates(0.8))
+    bpn = 200
+    if visc == "smagorinsky":
+        p.visc_kind, p.nu0, p.c_smag = capi.LBM_VISC_SMAGORINSKY, (0.8 - 0.5) / 3.0, 0.1
+        bpn = 236
     # warm-up on a short problem (kernel loading, allocator)
     u_w, F_w = u0.clone().requires_grad_(True), F.clone().requires_grad_(True)
     ag.strain_loss(u_w, F_w, ag.StrainLossProblem(p, 2 * every, every)).backward()
@@ -172,10 +179,11 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50
     t2 = time.perf_counter()
     # adjoint kernel alone
     N = n ** 3
-    sim = lbm.LBM(capi.Params(nx=n, ny=n, nz=n, s=rates(0.8), force_field=F.detach().reshape(3, N)))
-    jb = torch.zeros((1, 3, N), device="cuda")
-    sim.step(1, j_save=jb)
-    la = torch.randn((19, N), device="cuda")
+    p.force_field = F.detach().reshape(3, N)
+    sim = lbm.LBM(p)
+    jb = torch.zeros((1, sim.save_planes, N), device="cuda")
+    sim.step(1, save=jb)
+    la = torch.randn((sim.adjoint_planes, N), device="cuda")
     lb = torch.empty_like(la)
     gF = torch.zeros((3, N), device="cuda")
     for _ in range(3):
@@ -192,8 +200,8 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50
     fwd, bwd = t1 - t0, t2 - t1
     return {"J": J.item(), "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
             "backward_over_forward": round(bwd / fwd, 3),
-            "adjoint_kernel_ms": round(k_adj * 1e3, 4),
-            "adjoint_hbm_frac": round(200 * N / k_adj / 1e9 / HBM_PEAK_GBS, 4),
+            "adjoint_kernel_ms": round(k_adj * 1e3, 4), "adjoint_bytes_per_node": bpn,
+            "adjoint_hbm_frac": round(bpn * N / k_adj / 1e9 / HBM_PEAK_GBS, 4),
             "grad_u0_norm": float(u0.grad.norm()), "grad_F_norm": float(F.grad.norm())}
 
 
@@ -343,6 +351,9 @@ def main():
         result.setdefault("extra", {})
         result["extra"]["channel_powerlaw"] = channel_runs(torch, capi, lbm, max(1, args.steps // 2), args.warmup)
         result["extra"]["adjoint_c4"] = adjoint_run(torch, np, synth, capi, lbm, args.warmup)
+        torch.cuda.empty_cache()
+        result["extra"]["adjoint_c4_smagorinsky"] = adjoint_run(torch, np, synth, capi, lbm, args.warmup,
+                                                                visc="smagorinsky")
         result["extra"]["copy_GBps"] = copy_bandwidth(torch)
 
     if not args.no_cpu_baseline:

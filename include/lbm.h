@@ -128,10 +128,23 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
  *               the strain (formula `strain_kind`) of that step's pre-collision state; after
  *               the call it holds the strain of the state at level n_end - 1.
  *  strain_kind  LBM_STRAIN_YU or LBM_STRAIN_CHAI (ignored when S_out is NULL).
- *  j_save       device float[nsteps*3*N] or NULL: step k writes the momentum
- *               j = sum c g + F/2 used by its collision at offset k*3*N (for the adjoint).
+ *  save         device float[nsteps*R*N] or NULL, R = lbm_save_planes(ctx) (D3Q19 only):
+ *               step k writes at offset k*R*N the record its adjoint needs: planes 0..2 the
+ *               momentum j = sum c g + F/2 its collision used; for a strain-dependent
+ *               viscosity (R = 10) also planes 3..8, the non-equilibrium moments
+ *               m - m^eq of rows 1, 9, 11, 13, 14, 15 that enter Eq. LuoS, and plane 9, the
+ *               s_nu its strain was taken with (the lagged field value, or the implicitly
+ *               solved rate).
  */
-lbm_status lbm_step(lbm_ctx* ctx, int nsteps, float* S_out, int strain_kind, float* j_save, void* stream);
+lbm_status lbm_step(lbm_ctx* ctx, int nsteps, float* S_out, int strain_kind, float* save, void* stream);
+
+/* Planes per step of lbm_step's adjoint record: 3 (constant viscosity) or 10 (strain-dependent
+ * viscosity); 0 for D2Q9 or a NULL context. */
+int lbm_save_planes(const lbm_ctx* ctx);
+
+/* Planes of the adjoint state lam (each N floats): 19 (the populations), or 20 for the lagged
+ * viscosity kinds, whose plane 19 is the adjoint of the s_nu field; 0 for D2Q9 or NULL. */
+int lbm_adjoint_planes(const lbm_ctx* ctx);
 
 /* Strain of the current pre-collision state by the Yu (Eq. LuoS) or Chai (Eq. ChaiS)
  * formula, with the current s_nu field, into S_out (device float[6*N] / [3*N]). */
@@ -163,28 +176,37 @@ long long lbm_step_count(const lbm_ctx* ctx);
 lbm_status lbm_set_step_count(lbm_ctx* ctx, long long n);
 
 /*
- * Discrete adjoint (D3Q19, constant viscosity, periodic or walls_y). For one forward step
- * g^{n+1} = P C(g^n, F) (C the collision, P the pull streaming), given lam_in = dJ/dg^{n+1}
- * (canonical layout, device float[19*N]) and j_n (device float[3*N], the momentum that
- * step's collision used, as written by lbm_step's j_save), writes
- *   lam_out = (dC/dg)^T P^T lam_in              (device float[19*N])
+ * Discrete adjoint (D3Q19, periodic or walls_y, any viscosity kind; the paper has no adjoint).
+ * For one forward step g^{n+1} = P C(g^n, F) (C the collision, P the pull streaming), given
+ * lam_in = dJ/d(state^{n+1}) and rec_n, the record lbm_step's `save` wrote for step n
+ * (device float[lbm_save_planes(ctx)*N]), writes
+ *   lam_out = (dC/dg)^T P^T lam_in              (device float[A*N], A = lbm_adjoint_planes)
  * and, if grad_force is not NULL, accumulates (dC/dF)^T P^T lam_in into it (device
- * float[3*N], read-modify-write). lam_in and lam_out must not alias.
+ * float[3*N], read-modify-write). lam planes 0..18 are populations in canonical layout.
+ * Strain-dependent viscosity: the collision rate s_new is a function of the strain of
+ * Eq. LuoS (lagged: of the state and the s_nu field; implicit: solved with the strain), and
+ * its derivative enters the transpose; for the lagged kinds plane 19 of lam_in is dJ/d(s_nu
+ * field of step n+1) and plane 19 of lam_out dJ/d(s_nu field of step n). The power-law clamps
+ * and |S| = 0 take a zero derivative. lam_in and lam_out must not alias.
  */
-lbm_status lbm_adjoint_step(lbm_ctx* ctx, const float* j_n, const float* lam_in, float* lam_out,
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const float* rec_n, const float* lam_in, float* lam_out,
                             float* grad_force, void* stream);
 
 /*
  * Loss J = sum_x S:S of the current pre-collision state (Yu formula, which equals Chai,
- * Section 5.1), its gradient dJ/dg into lam_out (device float[19*N], canonical), and, if
- * grad_force is not NULL, dJ/dF (through j = sum c g + F/2) added into grad_force. J is
- * accumulated in FP64 and written to *J_host. Synchronises the stream.
+ * Section 5.1, at the rate the viscosity model gives the state: s_nu of the parameters, the
+ * lagged field, or the implicitly solved rate), its gradient into lam_out (device
+ * float[lbm_adjoint_planes(ctx)*N]: dJ/dg in canonical layout, plus dJ/d(s_nu field) in
+ * plane 19 for the lagged kinds), and, if grad_force is not NULL, dJ/dF (through
+ * j = sum c g + F/2) added into grad_force. J is accumulated in FP64 and written to *J_host.
+ * Synchronises the stream.
  */
 lbm_status lbm_strain_loss_seed(lbm_ctx* ctx, float* lam_out, float* grad_force, double* J_host, void* stream);
 
 /*
  * Adjoint of the initial state g^0 = g^eq(0, rho0 u0): grad_u0 (device float[3*N]) =
- * sum_i lam0_i dg^eq_i/du at u0 (rho_u: device float[4*N] as given to lbm_init).
+ * sum_i lam0_i dg^eq_i/du at u0 (rho_u: device float[4*N] as given to lbm_init). Only planes
+ * 0..18 of lam0 are read (the initial s_nu field does not depend on u0).
  */
 lbm_status lbm_init_adjoint(lbm_ctx* ctx, const float* rho_u, const float* lam0, float* grad_u0, void* stream);
 

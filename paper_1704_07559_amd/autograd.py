@@ -4,12 +4,14 @@
 
 S is the Yu strain (which equals the Chai strain, Section 5.1 of the paper) of the
 pre-collision state after N steps started from g^0 = g^eq(0, rho0 u0), with the body-force
-field F (Guo forcing) and a constant viscosity. ``backward`` runs the hand-written adjoint
-kernels of the library: the forward sweep stores the state every ``every`` steps; the
-reverse sweep reloads each checkpoint, recomputes its segment saving the momentum j of
-every step (3 floats per node per step), then applies lbm_adjoint_step backwards through
+field F (Guo forcing), at the rate the viscosity model gives it (constant, lagged
+Smagorinsky or power law, implicit Smagorinsky). ``backward`` runs the hand-written adjoint
+kernels of the library: the forward sweep stores the state (populations and, for the lagged
+models, the s_nu field) every ``every`` steps; the reverse sweep reloads each checkpoint,
+recomputes its segment saving the per-step adjoint record (3 floats per node for a constant
+viscosity: j; 10 for a strain-dependent one), then applies lbm_adjoint_step backwards through
 the segment; lbm_init_adjoint maps the last adjoint state onto u0. Peak extra memory:
-ceil(N/every) states plus ``every`` j fields.
+ceil(N/every) states plus ``every`` records.
 """
 from __future__ import annotations
 
@@ -23,7 +25,7 @@ from .lbm import LBM
 
 @dataclass
 class StrainLossProblem:
-    params: capi.Params   # D3Q19, constant viscosity; force / force_field are set per call
+    params: capi.Params   # D3Q19, any viscosity kind; force / force_field are set per call
     nsteps: int
     every: int = 50
 
@@ -43,7 +45,7 @@ class StrainLoss(torch.autograd.Function):
         for n0 in range(0, prob.nsteps, prob.every):
             checkpoints.append(sim.save_state())
             sim.step(min(prob.every, prob.nsteps - n0))
-        lam = torch.empty((19, N), dtype=torch.float32, device=u0.device)
+        lam = torch.empty((sim.adjoint_planes, N), dtype=torch.float32, device=u0.device)
         gF = torch.zeros((3, N), dtype=torch.float32, device=u0.device)
         J = capi.lbm_strain_loss_seed(sim.ctx, lam, gF)
         ctx.sim, ctx.checkpoints, ctx.lam, ctx.gF, ctx.rho_u, ctx.Ff = sim, checkpoints, lam, gF, rho_u, Ff
@@ -55,14 +57,14 @@ class StrainLoss(torch.autograd.Function):
         sim, prob, N = ctx.sim, ctx.prob, ctx.prob.params.N
         lam, gF = ctx.lam, ctx.gF
         lam2 = torch.empty_like(lam)
-        jbuf = torch.empty((prob.every, 3, N), dtype=torch.float32, device=lam.device)
+        rec = torch.empty((prob.every, sim.save_planes, N), dtype=torch.float32, device=lam.device)
         for seg in reversed(range(len(ctx.checkpoints))):
             n0 = seg * prob.every
             k = min(prob.every, prob.nsteps - n0)
             sim.load_state(ctx.checkpoints[seg])
-            sim.step(k, j_save=jbuf)
+            sim.step(k, save=rec)
             for n in reversed(range(k)):
-                capi.lbm_adjoint_step(sim.ctx, jbuf[n], lam, lam2, gF)
+                capi.lbm_adjoint_step(sim.ctx, rec[n], lam, lam2, gF)
                 lam, lam2 = lam2, lam
         gu = torch.empty((3, N), dtype=torch.float32, device=lam.device)
         capi.lbm_init_adjoint(sim.ctx, ctx.rho_u, lam, gu)

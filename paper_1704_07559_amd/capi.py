@@ -32,7 +32,7 @@ LBM_VISC_CONST, LBM_VISC_SMAGORINSKY, LBM_VISC_POWERLAW, LBM_VISC_SMAGORINSKY_IM
 EXPORTED = (
     "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_strain", "lbm_reduce", "lbm_get_populations",
     "lbm_set_populations", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count",
-    "lbm_set_step_count", "lbm_adjoint_step", "lbm_strain_loss_seed", "lbm_init_adjoint", "lbm_destroy",
+    "lbm_set_step_count", "lbm_save_planes", "lbm_adjoint_planes", "lbm_adjoint_step", "lbm_strain_loss_seed", "lbm_init_adjoint", "lbm_destroy",
     "lbm_status_string", "lbm_last_error",
 )
 
@@ -68,6 +68,8 @@ _sig = {
     "lbm_load_state": (ctypes.c_int, [_ctx_p, _vp, _vp]),
     "lbm_step_count": (ctypes.c_longlong, [_ctx_p]),
     "lbm_set_step_count": (ctypes.c_int, [_ctx_p, ctypes.c_longlong]),
+    "lbm_save_planes": (ctypes.c_int, [_ctx_p]),
+    "lbm_adjoint_planes": (ctypes.c_int, [_ctx_p]),
     "lbm_adjoint_step": (ctypes.c_int, [_ctx_p, _vp, _vp, _vp, _vp, _vp]),
     "lbm_strain_loss_seed": (ctypes.c_int, [_ctx_p, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "lbm_init_adjoint": (ctypes.c_int, [_ctx_p, _vp, _vp, _vp, _vp]),
@@ -182,8 +184,8 @@ def lbm_init(params: Params, f_a, f_b, s_nu_field=None, rho_u=None, grad_u=None,
     return ctx.value
 
 
-def lbm_step(ctx: int, nsteps: int = 1, S_out=None, strain_kind: int = LBM_STRAIN_YU, j_save=None, stream=None):
-    _check(_lib.lbm_step(ctx, int(nsteps), _ptr(S_out), int(strain_kind), _ptr(j_save), _stream(stream)), "lbm_step")
+def lbm_step(ctx: int, nsteps: int = 1, S_out=None, strain_kind: int = LBM_STRAIN_YU, save=None, stream=None):
+    _check(_lib.lbm_step(ctx, int(nsteps), _ptr(S_out), int(strain_kind), _ptr(save), _stream(stream)), "lbm_step")
 
 
 def lbm_strain(ctx: int, strain_kind: int, S_out, stream=None):
@@ -226,8 +228,16 @@ def lbm_set_step_count(ctx: int, n: int):
     _check(_lib.lbm_set_step_count(ctx, int(n)), "lbm_set_step_count")
 
 
-def lbm_adjoint_step(ctx: int, j_n, lam_in, lam_out, grad_force=None, stream=None):
-    _check(_lib.lbm_adjoint_step(ctx, _ptr(j_n), _ptr(lam_in), _ptr(lam_out), _ptr(grad_force), _stream(stream)),
+def lbm_save_planes(ctx: int) -> int:
+    return int(_lib.lbm_save_planes(ctx))
+
+
+def lbm_adjoint_planes(ctx: int) -> int:
+    return int(_lib.lbm_adjoint_planes(ctx))
+
+
+def lbm_adjoint_step(ctx: int, rec_n, lam_in, lam_out, grad_force=None, stream=None):
+    _check(_lib.lbm_adjoint_step(ctx, _ptr(rec_n), _ptr(lam_in), _ptr(lam_out), _ptr(grad_force), _stream(stream)),
            "lbm_adjoint_step")
 
 

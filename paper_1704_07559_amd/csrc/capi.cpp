@@ -143,6 +143,11 @@ lbm_status check_field(const void* p, const char* name) {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// Planes of the adjoint state: 19 populations, plus the s_nu field for the lagged kinds.
+int adjoint_planes(const lbm_ctx* c) {
+  return (c->V.kind == LBM_VISC_SMAGORINSKY || c->V.kind == LBM_VISC_POWERLAW) ? 20 : 19;
+}
+
 }  // namespace
 
 extern "C" {
@@ -205,15 +210,20 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
   return LBM_OK;
 }
 
-lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float* j_save, void* stream) {
+int lbm_save_planes(const lbm_ctx* c) { return (c && is3d(c)) ? save_planes(c->V) : 0; }
+
+int lbm_adjoint_planes(const lbm_ctx* c) { return (c && is3d(c)) ? adjoint_planes(c) : 0; }
+
+lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float* save, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   if (S_out && !aligned(S_out, 4)) return fail(LBM_EINVAL, "S_out must be 4-byte aligned");
   if (S_out && strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
-  if (j_save && !aligned(j_save, 4)) return fail(LBM_EINVAL, "j_save must be 4-byte aligned");
-  if (j_save && !is3d(c)) return fail(LBM_EUNSUPPORTED, "j_save is provided for D3Q19 only");
+  if (save && !aligned(save, 4)) return fail(LBM_EINVAL, "save must be 4-byte aligned");
+  if (save && !is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 only");
+  const size_t rec_elems = static_cast<size_t>(is3d(c) ? save_planes(c->V) : 0) * c->G.N;
   const hipStream_t s = as_stream(stream);
   for (int n = 0; n < nsteps; ++n) {
     StepIO io;
@@ -222,7 +232,7 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
     io.snu = c->snu;
     io.S_out = S_out;
     io.emit = S_out ? strain_kind : 0;
-    io.j_save = j_save ? j_save + static_cast<size_t>(n) * 3 * c->G.N : nullptr;
+    io.save = save ? save + static_cast<size_t>(n) * rec_elems : nullptr;
     hipError_t e = is3d(c) ? d3q19::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s)
                            : d2q9::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
@@ -319,22 +329,22 @@ lbm_status lbm_set_step_count(lbm_ctx* c, long long n) {
   return LBM_OK;
 }
 
-lbm_status lbm_adjoint_step(lbm_ctx* c, const float* j_n, const float* lam_in, float* lam_out, float* grad_force,
+lbm_status lbm_adjoint_step(lbm_ctx* c, const float* rec_n, const float* lam_in, float* lam_out, float* grad_force,
                             void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
   if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
-  if (c->V.kind != LBM_VISC_CONST) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for a constant viscosity");
-  if ((st = check_field(j_n, "j_n")) != LBM_OK) return st;
+  if ((st = check_field(rec_n, "rec_n")) != LBM_OK) return st;
   if ((st = check_field(lam_in, "lam_in")) != LBM_OK) return st;
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
   if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
   {
     const uintptr_t a = reinterpret_cast<uintptr_t>(lam_in), b = reinterpret_cast<uintptr_t>(lam_out);
-    if ((a < b ? b - a : a - b) < sizeof(float) * 19 * static_cast<size_t>(c->G.N))
+    if ((a < b ? b - a : a - b) < sizeof(float) * adjoint_planes(c) * static_cast<size_t>(c->G.N))
       return fail(LBM_EINVAL, "lam_in and lam_out overlap");
   }
-  hipError_t e = d3q19::launch_adjoint_step(c->G, c->M, c->F, j_n, lam_in, lam_out, grad_force, as_stream(stream));
+  hipError_t e = d3q19::launch_adjoint_step(c->G, c->M, c->V, c->F, rec_n, lam_in, lam_out, grad_force,
+                                            as_stream(stream));
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step");
 }
 
@@ -342,15 +352,14 @@ lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, d
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
   if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
-  if (c->V.kind != LBM_VISC_CONST) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for a constant viscosity");
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
   if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
   if (!J_host) return fail(LBM_EINVAL, "J_host is NULL");
   const hipStream_t s = as_stream(stream);
   double* partials = c->scratch;
   double* dout = c->scratch + static_cast<size_t>(kReduceBlocks) * kReduceVals;
-  hipError_t e = d3q19::launch_loss_seed(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], lam_out, grad_force, partials,
-                                         dout, s);
+  hipError_t e = d3q19::launch_loss_seed(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, lam_out,
+                                         grad_force, partials, dout, s);
   if (e != hipSuccess) return hip_fail(e, "lbm_strain_loss_seed");
   double out[kReduceVals];
   e = hipMemcpyAsync(out, dout, sizeof(out), hipMemcpyDeviceToHost, s);

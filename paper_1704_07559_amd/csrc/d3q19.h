@@ -182,6 +182,9 @@ __device__ __forceinline__ float delta_rho(const Pairs& P) {
 // Non-equilibrium moments m_k - m_k^eq for the non-conserved rows (Eq. meq, with rows 9..12
 // as in the equilibrium column of Eq. solvem). Index k of the returned array is row k;
 // rows 0, 3, 5, 7 are not filled.
+// Rows relaxed with s_nu (Eq. sD3Q15meaning).
+constexpr bool is_nu_slot(int k) { return k == 9 || k == 11 || k == 13 || k == 14 || k == 15; }
+
 struct Neq {
   float m[Q];
 };
@@ -295,6 +298,15 @@ __device__ __forceinline__ float implicit_smagorinsky(const float (&P)[6], const
     s -= f / (c + k * r + s * k * dr);
   }
   return s;
+}
+
+// The implicit Smagorinsky rate at one node from the Yu strain of the non-equilibrium
+// moments (the Chai strain is the same function of the state, Section 5.1).
+__device__ __forceinline__ float implicit_rate_yu(const Neq& n, const ModelF& M, const ViscF& V) {
+  float P[6], A[6];
+  strain_yu(n, M.s[1], 0.0f, M.inv_rho0, P);
+  strain_yu(n, 0.0f, 1.0f, M.inv_rho0, A);
+  return implicit_smagorinsky(P, A, V.nu0, V.csmag2);
 }
 
 // Guo force moments S_F = T F-bar with F-bar_i = (d g^eq_i / d j) . F (He-Luo equilibrium

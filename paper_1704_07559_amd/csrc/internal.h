@@ -167,6 +167,14 @@ __device__ __forceinline__ float viscous_rate(float SS, const ViscF& V) {
   return 1.0f / (3.0f * nu + 0.5f);
 }
 
+// d nu / d gamma of the lagged models (zero where the power law is clamped or gamma = 0).
+__device__ __forceinline__ float viscous_slope(float gamma, const ViscF& V) {
+  if (V.kind == 1) return V.csmag2;
+  if (!(gamma > 0.0f)) return 0.0f;
+  const float nu = V.Kpl * powf(gamma, V.npl - 1.0f);
+  return (nu > V.numin && nu < V.numax) ? (V.npl - 1.0f) * nu / gamma : 0.0f;
+}
+
 // Launch shape for the node-parallel kernels: one thread per node, blocks of (TX, TY)
 // nodes (at most kMaxBlock threads), grid (ceil(nx/TX), ceil(ny/TY), nz).
 constexpr int kMaxBlock = 256;
@@ -203,8 +211,12 @@ struct StepIO {
   float* snu;     // lagged s_nu field (variable viscosity) or nullptr
   float* S_out;   // strain output or nullptr
   int emit;       // 1 Yu, 2 Chai
-  float* j_save;  // 3*N or nullptr
+  float* save;    // per-step adjoint record (save_planes(V) * N floats) or nullptr
 };
+
+// Planes of the per-step record the step writes for the adjoint: j (3), plus, for a
+// strain-dependent viscosity, m^neq of rows 1, 9, 11, 13, 14, 15 and the strain's s_nu.
+inline int save_planes(const ViscF& V) { return V.kind == 0 ? 3 : 10; }
 
 // Reductions: 8 doubles per block, then one block sums the partials in a fixed order.
 constexpr int kReduceBlocks = 1024;
@@ -222,10 +234,11 @@ hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hi
 hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
 hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
                          const float* snu, double* partials, double* out, hipStream_t);
-hipError_t launch_adjoint_step(const Geo&, const ModelF&, const ForceF&, const float* j_n, const float* lam_in,
-                               float* lam_out, float* grad_force, hipStream_t);
-hipError_t launch_loss_seed(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, float* lam_out,
-                            float* grad_force, double* partials, double* out, hipStream_t);
+hipError_t launch_adjoint_step(const Geo&, const ModelF&, const ViscF&, const ForceF&, const float* rec,
+                               const float* lam_in, float* lam_out, float* grad_force, hipStream_t);
+hipError_t launch_loss_seed(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                            const float* snu, float* lam_out, float* grad_force, double* partials, double* out,
+                            hipStream_t);
 hipError_t launch_init_adjoint(const Geo&, const ModelF&, const float* rho_u, const float* lam0, float* grad_u0,
                                hipStream_t);
 }  // namespace d3q19

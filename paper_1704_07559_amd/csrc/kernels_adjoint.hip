@@ -1,4 +1,5 @@
-// Discrete adjoint of the D3Q19 step (constant viscosity) and of the strain-squared loss.
+// Discrete adjoint of the D3Q19 step and of the strain-squared loss, for a constant or a
+// strain-dependent viscosity.
 //
 // Forward step: g^{n+1} = P C(g^n, F), with the collision of Eq. mrteqvT written in moment
 // space, m* = m - L (m - m^eq(drho, j)) + (I - L/2) S_F(j, F), j = (m_3, m_5, m_7) + F/2,
@@ -12,6 +13,15 @@
 // E = dm^eq/dm has non-zero columns 0 (d/d drho) and 3, 5, 7 (d/dj); G(j) = dS_F/dF.
 // All derivative rows are written from Eq. meq (rows 9..12 as in Eq. solvem) and from the
 // Guo moments of the He-Luo equilibrium.
+//
+// Strain-dependent viscosity: L = L(s_new) with s_new a function of the strain of Eq. LuoS,
+// S = (Y_e + s Y_n) m^neq (affine in the rate s it is taken with). Lagged kinds: s = the
+// s_nu field (state), s_new = h(|S|), h = 1/(3 nu + 1/2), and s_new becomes the next field;
+// implicit kind: s = s_new solves s (3 nu(|S(s)|) + 1/2) = 1. The step's transpose gains a
+// rank-one term: sigma = dJ/ds_new = -sum_{k nu rows} mu_k (m^neq_k + S_F,k / 2) (+ the
+// adjoint of the field s_new is written to), then dJ/dm^neq = Y(s)^T (c dgamma/dS) with
+// c = sigma h'(gamma) (lagged) or -sigma s k / (dG/ds) (implicit, k = 3 C_s^2), mapped through
+// m^neq = m - m^eq(drho, j).
 #include <hip/hip_runtime.h>
 
 #include "d3q19.h"
@@ -76,9 +86,68 @@ __device__ __forceinline__ void force_at(const ForceF& Fo, unsigned N, unsigned 
   }
 }
 
-__global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, ForceF Fo, const float* __restrict__ j_n,
-                                                      const float* __restrict__ lam_in, float* __restrict__ lam_out,
-                                                      float* __restrict__ grad_force) {
+// Rows 1, 9, 11, 13, 14, 15 of Y(s)^T d, with S = Y(s) m^neq the Yu strain of Eq. LuoS at
+// s_e = s1, s_nu = s (d = dJ/dS, off-diagonal components once).
+struct YuT {
+  float r1, r9, r11, r13, r14, r15;
+};
+__device__ __forceinline__ YuT yu_transpose(const float (&d)[6], float s1, float s, float ir) {
+  YuT o;
+  o.r1 = -s1 * ir * (1.0f / 38.0f) * (d[0] + d[1] + d[2]);
+  o.r9 = s * ir * (-0.5f * d[0] + 0.25f * (d[1] + d[2]));
+  o.r11 = s * ir * 0.75f * (d[2] - d[1]);
+  o.r13 = -1.5f * s * ir * d[3];
+  o.r14 = -1.5f * s * ir * d[4];
+  o.r15 = -1.5f * s * ir * d[5];
+  return o;
+}
+
+// (d m^eq / d j)^T y for y on rows 1, 9, 11, 13, 14, 15 (Eq. meq).
+__device__ __forceinline__ void meq_j_transpose(const YuT& y, float jx, float jy, float jz, float ir, float& bx,
+                                                float& by, float& bz) {
+  bx = (38.0f * jx * y.r1 + 4.0f * jx * y.r9 + jy * y.r13 + jz * y.r15) * ir;
+  by = (38.0f * jy * y.r1 - 2.0f * jy * y.r9 + 2.0f * jy * y.r11 + jx * y.r13 + jz * y.r14) * ir;
+  bz = (38.0f * jz * y.r1 - 2.0f * jz * y.r9 - 2.0f * jz * y.r11 + jy * y.r14 + jx * y.r15) * ir;
+}
+
+// Strain S = P + s A from the six non-equilibrium moments of Eq. LuoS: P the s_e part, A the
+// s_nu part at unit rate; gamma = |S| = sqrt(2 S:S) and dgamma/dS = 2 W S / gamma.
+struct StrainParts {
+  float A[6], S[6], dg[6], ss, gamma;
+};
+__device__ __forceinline__ StrainParts strain_parts(const float (&mn)[6], float s1, float s, float ir) {
+  Neq n;
+  n.m[1] = mn[0];
+  n.m[9] = mn[1];
+  n.m[11] = mn[2];
+  n.m[13] = mn[3];
+  n.m[14] = mn[4];
+  n.m[15] = mn[5];
+  StrainParts o;
+  float P[6];
+  strain_yu(n, s1, 0.0f, ir, P);
+  strain_yu(n, 0.0f, 1.0f, ir, o.A);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o.S[c] = __builtin_fmaf(s, o.A[c], P[c]);
+  o.ss = o.S[0] * o.S[0] + o.S[1] * o.S[1] + o.S[2] * o.S[2] +
+         2.0f * (o.S[3] * o.S[3] + o.S[4] * o.S[4] + o.S[5] * o.S[5]);
+  o.gamma = sqrtf(2.0f * o.ss);
+  const float k = o.gamma > 0.0f ? 2.0f / o.gamma : 0.0f;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o.dg[c] = (c < 3 ? k : 2.0f * k) * o.S[c];
+  return o;
+}
+
+// One reverse step. VISC: strain-dependent viscosity (kind 1, 2 lagged; 3 implicit), where
+// the collision rate s_new depends on the state: the record of the forward step holds j,
+// m^neq of rows 1, 9, 11, 13, 14, 15 and the strain's rate s_x; for the lagged kinds plane 19
+// of lam_in / lam_out is the adjoint of the s_nu field (not streamed).
+template <bool VISC>
+__global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, ViscF V, ForceF Fo,
+                                                            const float* __restrict__ rec,
+                                                            const float* __restrict__ lam_in,
+                                                            float* __restrict__ lam_out,
+                                                            float* __restrict__ grad_force) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -86,6 +155,7 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, For
   const Nbr ne = neighbours(G, x, y, z);
   const unsigned self = ne.self;
   const Nbr nb = in_bytes<float>(ne);
+  const size_t N = G.N;
 
   float lt[Q];
   pull<LatRev, float>(lam_in, G, nb, y, lt);
@@ -98,12 +168,22 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, For
     mu[k] = moment<k>(P) * (1.0f / static_cast<float>(DV.D[k]));
   });
 
-  const float jx = j_n[self], jy = j_n[G.N + self], jz = j_n[2 * static_cast<size_t>(G.N) + self];
+  const float jx = rec[self], jy = rec[N + self], jz = rec[2 * N + self];
   const float ir = M.inv_rho0;
+  float snu = M.s[9];
+  float mn[6], sx = 0.0f;
+  StrainParts sp;
+  if constexpr (VISC) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) mn[c] = rec[(3 + c) * N + self];
+    sx = rec[9 * N + self];
+    sp = strain_parts(mn, M.s[1], sx, ir);
+    snu = V.kind == 3 ? sx : viscous_rate(sp.ss, V);
+  }
   float w[Q], v[Q], nu[Q];
   static_for<Q>([&](auto ki) {
     constexpr int k = ki;
-    const float sk = M.s[k];
+    const float sk = is_nu_slot(k) ? snu : M.s[k];
     w[k] = sk * mu[k];
     v[k] = (1.0f - 0.5f * sk) * mu[k];
     nu[k] = mu[k] - w[k];
@@ -134,6 +214,51 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, For
   nu[5] += Ay + By;
   nu[7] += Az + Bz;
 
+  float gbx = 0.f, gby = 0.f, gbz = 0.f;  // extra dJ/dF through the rate
+  if constexpr (VISC) {
+    // sensitivity of J to this collision's rate: dm*_k/ds = -(m^neq_k + S_F,k / 2) on the
+    // s_nu rows, plus the adjoint of the s_nu field this collision writes (lagged kinds)
+    float SF9 = 0.f, SF11 = 0.f, SF13 = 0.f, SF14 = 0.f, SF15 = 0.f;
+    if (Fo.mode) {
+      SF9 = (4.0f * jx * Fx - 2.0f * jy * Fy - 2.0f * jz * Fz) * ir;
+      SF11 = (2.0f * jy * Fy - 2.0f * jz * Fz) * ir;
+      SF13 = (jx * Fy + jy * Fx) * ir;
+      SF14 = (jy * Fz + jz * Fy) * ir;
+      SF15 = (jx * Fz + jz * Fx) * ir;
+    }
+    float sigma = -(mu[9] * (mn[1] + 0.5f * SF9) + mu[11] * (mn[2] + 0.5f * SF11) + mu[13] * (mn[3] + 0.5f * SF13) +
+                    mu[14] * (mn[4] + 0.5f * SF14) + mu[15] * (mn[5] + 0.5f * SF15));
+    const bool lagged = V.kind != 3;
+    if (lagged) sigma += lam_in[19 * N + self];
+    float dA = 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dA += sp.dg[c] * sp.A[c];
+    float cg;  // dJ/dgamma through the rate
+    if (lagged) {
+      cg = sigma * (-3.0f * viscous_slope(sp.gamma, V) * snu * snu);
+    } else {
+      const float c0 = 3.0f * V.nu0 + 0.5f, k = 3.0f * V.csmag2;
+      cg = -sigma * snu * k / (c0 + k * sp.gamma + snu * k * dA);
+    }
+    float d6[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) d6[c] = cg * sp.dg[c];
+    if (lagged) lam_out[19 * N + self] = cg * dA;
+    // dJ/dm^neq = Y(s_x)^T d6; m^neq = m - m^eq(drho, j): (I - E)^T on it
+    const YuT yv = yu_transpose(d6, M.s[1], sx, ir);
+    meq_j_transpose(yv, jx, jy, jz, ir, gbx, gby, gbz);
+    nu[0] += 11.0f * yv.r1;
+    nu[1] += yv.r1;
+    nu[9] += yv.r9;
+    nu[11] += yv.r11;
+    nu[13] += yv.r13;
+    nu[14] += yv.r14;
+    nu[15] += yv.r15;
+    nu[3] -= gbx;
+    nu[5] -= gby;
+    nu[7] -= gbz;
+  }
+
   float lo[Q];
   apply_transpose(nu, lo);
   store_local<Q>(lam_out, G, nb.self, lo);
@@ -146,17 +271,19 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, For
                       jy * v[12] + jx * v[13] + jz * v[14]) * ir + v[5] - (2.0f / 3.0f) * v[6];
     const float Cz = (38.0f * jz * v[1] - 11.0f * jz * v[2] - 2.0f * jz * v[9] + jz * v[10] - 2.0f * jz * v[11] +
                       jz * v[12] + jy * v[14] + jx * v[15]) * ir + v[7] - (2.0f / 3.0f) * v[8];
-    grad_force[self] += 0.5f * (Ax + Bx) + Cx;
-    grad_force[G.N + self] += 0.5f * (Ay + By) + Cy;
-    grad_force[2 * static_cast<size_t>(G.N) + self] += 0.5f * (Az + Bz) + Cz;
+    grad_force[self] += 0.5f * (Ax + Bx - gbx) + Cx;
+    grad_force[N + self] += 0.5f * (Ay + By - gby) + Cy;
+    grad_force[2 * N + self] += 0.5f * (Az + Bz - gbz) + Cz;
   }
 }
 
-// Loss J = sum_x S:S (Yu strain of the current pre-collision state) and its gradients.
+// Loss J = sum_x S:S (Yu strain of the current pre-collision state, at the rate the model
+// gives it: s_nu of p, the lagged field, or the implicitly solved rate) and its gradients.
+// For the lagged kinds plane 19 of lam_out receives dJ/d(s_nu field).
 template <typename S>
-__global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ForceF Fo, const S* __restrict__ buf,
-                                                        float* __restrict__ lam_out, float* __restrict__ grad_force,
-                                                        double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* __restrict__ buf,
+                                                        const float* __restrict__ snu_f, float* __restrict__ lam_out,
+                                                        float* __restrict__ grad_force, double* __restrict__ partials) {
   double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
   const unsigned stride = gridDim.x * blockDim.x;
   for (unsigned idx = blockIdx.x * blockDim.x + threadIdx.x; idx < G.N; idx += stride) {
@@ -174,32 +301,51 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ForceF 
     force_at(Fo, G.N, self, Fx, Fy, Fz);
     const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
     const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
-    float S6[6];
-    const float s1 = M.s[1], sn = M.s[9], ir = M.inv_rho0;
-    strain_yu(n, s1, sn, ir, S6);
+    const float s1 = M.s[1], ir = M.inv_rho0;
+    float sn = M.s[9];
+    if (V.kind == 3) sn = implicit_rate_yu(n, M, V);
+    else if (V.kind != 0) sn = snu_f[self];
+    const float mn[6] = {n.m[1], n.m[9], n.m[11], n.m[13], n.m[14], n.m[15]};
+    const StrainParts sp = strain_parts(mn, s1, sn, ir);
+    const float* S6 = sp.S;
     acc[0] += static_cast<double>(S6[0]) * S6[0] + static_cast<double>(S6[1]) * S6[1] +
               static_cast<double>(S6[2]) * S6[2] +
               2.0 * (static_cast<double>(S6[3]) * S6[3] + static_cast<double>(S6[4]) * S6[4] +
                      static_cast<double>(S6[5]) * S6[5]);
-    // sigma = Y^T (2 W S): derivatives of Eq. LuoS with respect to m1, m9, m11, m13..15
-    const float d0 = 2.0f * S6[0], d1 = 2.0f * S6[1], d2 = 2.0f * S6[2];
-    const float d3 = 4.0f * S6[3], d4 = 4.0f * S6[4], d5 = 4.0f * S6[5];
+    // dJ/dS = 2 W S, and dJ/ds = (2 W S) . A at the strain's rate
+    float d6[6] = {2.0f * S6[0], 2.0f * S6[1], 2.0f * S6[2], 4.0f * S6[3], 4.0f * S6[4], 4.0f * S6[5]};
+    float dJds = 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dJds += d6[c] * sp.A[c];
+    if (V.kind == 3) {
+      // the implicit rate moves with the state: ds/dm^neq = -k s (dgamma/dS)^T Y(s) / dG/ds
+      float dA = 0.f;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) dA += sp.dg[c] * sp.A[c];
+      const float c0 = 3.0f * V.nu0 + 0.5f, k = 3.0f * V.csmag2;
+      const float cg = -dJds * sn * k / (c0 + k * sp.gamma + sn * k * dA);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) d6[c] = __builtin_fmaf(cg, sp.dg[c], d6[c]);
+    } else if (V.kind != 0) {
+      lam_out[19 * static_cast<size_t>(G.N) + self] = dJds;
+    }
+    // sigma = Y(s)^T dJ/dS on rows 1, 9, 11, 13..15 of m^neq
+    const YuT yv = yu_transpose(d6, s1, sn, ir);
     float sg[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) sg[k] = 0.0f;
-    sg[1] = -s1 * ir * (1.0f / 38.0f) * (d0 + d1 + d2);
-    sg[9] = sn * ir * (-0.5f * d0 + 0.25f * (d1 + d2));
-    sg[11] = sn * ir * 0.75f * (d2 - d1);
-    sg[13] = -1.5f * sn * ir * d3;
-    sg[14] = -1.5f * sn * ir * d4;
-    sg[15] = -1.5f * sn * ir * d5;
+    sg[1] = yv.r1;
+    sg[9] = yv.r9;
+    sg[11] = yv.r11;
+    sg[13] = yv.r13;
+    sg[14] = yv.r14;
+    sg[15] = yv.r15;
     // lam = T^T sigma - (dm^eq/dg)^T sigma,  (dm^eq/dg)^T sigma = a 1 + C^T b
     float lam[Q];
     apply_transpose(sg, lam);
     const float a = -11.0f * sg[1];
-    const float bx = (38.0f * jx * sg[1] + 4.0f * jx * sg[9] + jy * sg[13] + jz * sg[15]) * ir;
-    const float by = (38.0f * jy * sg[1] - 2.0f * jy * sg[9] + 2.0f * jy * sg[11] + jx * sg[13] + jz * sg[14]) * ir;
-    const float bz = (38.0f * jz * sg[1] - 2.0f * jz * sg[9] - 2.0f * jz * sg[11] + jy * sg[14] + jx * sg[15]) * ir;
+    float bx, by, bz;
+    meq_j_transpose(yv, jx, jy, jz, ir, bx, by, bz);
     static_for<Q>([&](auto ii) {
       constexpr int i = ii;
       lam[i] -= a + static_cast<float>(CX[i]) * bx + static_cast<float>(CY[i]) * by + static_cast<float>(CZ[i]) * bz;
@@ -240,21 +386,25 @@ __global__ __launch_bounds__(kMaxBlock) void init_adjoint_kernel(Geo G, ModelF M
   grad_u0[2 * N + self] = M.rho0 * (gz - 3.0f * uz * sl);
 }
 
-hipError_t launch_adjoint_step(const Geo& G, const ModelF& M, const ForceF& Fo, const float* j_n, const float* lam_in,
-                               float* lam_out, float* grad_force, hipStream_t st) {
+hipError_t launch_adjoint_step(const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const float* rec,
+                               const float* lam_in, float* lam_out, float* grad_force, hipStream_t st) {
   const Launch L = node_launch(G);
-  hipLaunchKernelGGL(adjoint_kernel, L.grid, L.block, 0, st, G, M, Fo, j_n, lam_in, lam_out, grad_force);
+  if (V.kind == 0)
+    hipLaunchKernelGGL(adjoint_kernel<false>, L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+  else
+    hipLaunchKernelGGL(adjoint_kernel<true>, L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
   return hipGetLastError();
 }
 
-hipError_t launch_loss_seed(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
-                            float* lam_out, float* grad_force, double* partials, double* out, hipStream_t st) {
+hipError_t launch_loss_seed(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo,
+                            const void* buf, const float* snu, float* lam_out, float* grad_force, double* partials,
+                            double* out, hipStream_t st) {
   unsigned nb = (G.N + 255) / 256;
   if (nb > static_cast<unsigned>(kReduceBlocks)) nb = kReduceBlocks;
   switch (storage) {
-    case 0: hipLaunchKernelGGL(loss_seed_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, Fo, static_cast<const float*>(buf), lam_out, grad_force, partials); break;
-    case 1: hipLaunchKernelGGL(loss_seed_kernel<_Float16>, dim3(nb), dim3(256), 0, st, G, M, Fo, static_cast<const _Float16*>(buf), lam_out, grad_force, partials); break;
-    case 2: hipLaunchKernelGGL(loss_seed_kernel<__bf16>, dim3(nb), dim3(256), 0, st, G, M, Fo, static_cast<const __bf16*>(buf), lam_out, grad_force, partials); break;
+    case 0: hipLaunchKernelGGL(loss_seed_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, static_cast<const float*>(buf), snu, lam_out, grad_force, partials); break;
+    case 1: hipLaunchKernelGGL(loss_seed_kernel<_Float16>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, static_cast<const _Float16*>(buf), snu, lam_out, grad_force, partials); break;
+    case 2: hipLaunchKernelGGL(loss_seed_kernel<__bf16>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, static_cast<const __bf16*>(buf), snu, lam_out, grad_force, partials); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

@@ -25,8 +25,6 @@ struct Lat {
   static constexpr int opp(int i) { return DV.opp[i]; }
 };
 
-constexpr bool is_nu_slot(int k) { return k == 9 || k == 11 || k == 13 || k == 14 || k == 15; }
-
 __device__ __forceinline__ void load_force(const ForceF& Fo, unsigned N, unsigned self, float& Fx, float& Fy,
                                            float& Fz) {
   if (Fo.mode == 1) {
@@ -93,9 +91,11 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
 
   float Syu[6], Sch[6];
   float snu = M.s[9];
+  float s_strain;  // the s_nu this step's strain is taken with
   if (V.kind == 3) {
     // implicit coupling: the strain at the rate of this very collision
     snu = implicit_rate(P_, drho, jx, jy, jz, n, M, V);
+    s_strain = snu;
     if (io.S_out) {
       if (io.emit == 2) {
         float r[Q];
@@ -110,6 +110,7 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
   } else {
     // lagged coupling: the strain of the incoming state with the rates of the previous collision
     const float snu_prev = io.snu ? io.snu[self] : M.s[9];
+    s_strain = snu_prev;
     const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
     const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
     if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
@@ -155,10 +156,22 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
   }
   add_back_transform(dm, g);
 
-  if (io.j_save) {
-    io.j_save[self] = jx;
-    io.j_save[G.N + self] = jy;
-    io.j_save[2 * static_cast<size_t>(G.N) + self] = jz;
+  if (io.save) {
+    // what the adjoint of this step needs: j, and for a strain-dependent viscosity the
+    // non-equilibrium moments entering Eq. LuoS and the rate the strain was taken with
+    const size_t N = G.N;
+    io.save[self] = jx;
+    io.save[N + self] = jy;
+    io.save[2 * N + self] = jz;
+    if (V.kind != 0) {
+      io.save[3 * N + self] = n.m[1];
+      io.save[4 * N + self] = n.m[9];
+      io.save[5 * N + self] = n.m[11];
+      io.save[6 * N + self] = n.m[13];
+      io.save[7 * N + self] = n.m[14];
+      io.save[8 * N + self] = n.m[15];
+      io.save[9 * N + self] = s_strain;
+    }
   }
 }
 

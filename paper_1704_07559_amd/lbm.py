@@ -57,8 +57,17 @@ class LBM:
         return 6 if self.params.lattice == capi.LBM_D3Q19 else 3
 
     def step(self, nsteps: int = 1, S_out: Optional[torch.Tensor] = None, strain_kind: int = capi.LBM_STRAIN_YU,
-             j_save: Optional[torch.Tensor] = None):
-        capi.lbm_step(self.ctx, nsteps, S_out, strain_kind, j_save)
+             save: Optional[torch.Tensor] = None):
+        """Advance nsteps; ``save`` (nsteps x save_planes x N floats) receives the adjoint record."""
+        capi.lbm_step(self.ctx, nsteps, S_out, strain_kind, save)
+
+    @property
+    def save_planes(self) -> int:
+        return capi.lbm_save_planes(self.ctx)
+
+    @property
+    def adjoint_planes(self) -> int:
+        return capi.lbm_adjoint_planes(self.ctx)
 
     def strain(self, kind: int = capi.LBM_STRAIN_YU) -> torch.Tensor:
         S = torch.empty((self.ncomp,) + self.shape, dtype=torch.float32, device=self.device)

@@ -38,7 +38,7 @@ def test_adjoint_step_matches_oracle(walls):
     sim.set_populations(torch.as_tensor(g.astype(np.float32)).cuda())
     N = cp.N
     jbuf = torch.empty((1, 3, N), device="cuda")
-    sim.step(1, j_save=jbuf)      # saves j of the collision of state g
+    sim.step(1, save=jbuf)      # saves j of the collision of state g
     lam_in = synth.random_state(19, shape, seed=4, scale=1.0)
     lam_t = torch.as_tensor(lam_in.astype(np.float32)).cuda().reshape(19, N).contiguous()
     lam_out = torch.empty_like(lam_t)

@@ -189,11 +189,16 @@ def test_error_paths_return_status_without_launching():
     sim = lbm.LBM(cp)
     before = sim.populations().clone()
     N = cp.N
-    lam = torch.zeros((19, N), device="cuda")
+    lam = torch.zeros((sim.adjoint_planes, N), device="cuda")
+    rec = torch.zeros((sim.save_planes, N), device="cuda")
+    p2 = capi.Params(nx=16, ny=8, nz=1, lattice=capi.LBM_D2Q9, s=[0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 1.25, 1.25])
+    sim2 = lbm.LBM(p2)
     for call, status in (
-        (lambda: capi.lbm_adjoint_step(sim.ctx, torch.zeros((3, N), device="cuda"), lam, torch.empty_like(lam)),
-         capi.LBM_EUNSUPPORTED),                                   # variable viscosity
-        (lambda: capi.lbm_strain_loss_seed(sim.ctx, lam), capi.LBM_EUNSUPPORTED),
+        (lambda: capi.lbm_adjoint_step(sim.ctx, None, lam, torch.empty_like(lam)), capi.LBM_EINVAL),
+        (lambda: capi.lbm_adjoint_step(sim.ctx, rec, lam, lam), capi.LBM_EINVAL),          # aliasing
+        (lambda: capi.lbm_adjoint_step(sim2.ctx, rec, lam, torch.empty_like(lam)), capi.LBM_EUNSUPPORTED),
+        (lambda: capi.lbm_strain_loss_seed(sim2.ctx, lam), capi.LBM_EUNSUPPORTED),         # D2Q9
+        (lambda: capi.lbm_step(sim2.ctx, 1, None, capi.LBM_STRAIN_YU, rec), capi.LBM_EUNSUPPORTED),
         (lambda: capi.lbm_step(sim.ctx, -1), capi.LBM_EINVAL),
         (lambda: capi.lbm_step(sim.ctx, 1, torch.empty((6, N), device="cuda"), 7), capi.LBM_EINVAL),
         (lambda: capi.lbm_strain(sim.ctx, capi.LBM_STRAIN_YU, None), capi.LBM_EINVAL),
@@ -204,6 +209,8 @@ def test_error_paths_return_status_without_launching():
     sim.step(0)
     assert torch.equal(sim.populations(), before)
     assert sim.step_count == 0
+    sim2.close()
+    sim.close()
 
 
 def test_adjoint_lam_aliasing_rejected():
