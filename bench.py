@@ -33,9 +33,11 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS & % HBM roofline, D3Q19 MRT+strain, FP32 vs FP16-stored; adjoint/fwd cost"
+# The sources the D3Q19 step kernel is compiled from (launch.h holds host-side
+# declarations only and is left out).
 KERNEL_SOURCES = ["paper_1704_07559_amd/csrc/kernels_d3q19.hip", "paper_1704_07559_amd/csrc/d3q19.h",
                   "paper_1704_07559_amd/csrc/internal.h", "paper_1704_07559_amd/csrc/codec.h",
-                  "paper_1704_07559_amd/csrc/static_for.h"]
+                  "paper_1704_07559_amd/csrc/static_for.h", "paper_1704_07559_amd/csrc/reduce.h"]
 
 
 def log(msg):
@@ -72,6 +74,14 @@ def rates(tau_nu):
     # d'Humieres rates with s_nu = 1/tau_nu in slots 9, 11, 13, 14, 15
     sn = 1.0 / tau_nu
     return [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sn, 1.4, sn, 1.4, sn, sn, sn, 1.98, 1.98, 1.98]
+
+
+def rates15(tau_nu):
+    """D3Q15 relaxation rates (rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, p_ww, p_xy,
+    p_yz, p_xz, m_xyz): s_e = 1.6, s_eps = 1.2, s_q = 1.6, s_m = 1.2 (d'Humieres et al. 2002),
+    s_nu = 1/tau_nu."""
+    sn = 1.0 / tau_nu
+    return [0.0, 1.6, 1.2, 0.0, 1.6, 0.0, 1.6, 0.0, 1.6, sn, sn, sn, sn, sn, 1.2]
 
 
 def les_params(capi, n, storage):
@@ -345,6 +355,22 @@ def main():
                                                 "kernel_ms": round(ki * 1e3, 4), "bytes_per_node": 152,
                                                 "hbm_frac": round(152 * N / ki / 1e9 / HBM_PEAK_GBS, 4),
                                                 "ke": di["ke"], "nonfinite": di["nonfinite"]}
+        # the same LES on the D3Q15 lattice (Yu-type formula of the Section 5.4 route):
+        # 15 x 4 B read + written + 8 B lagged s_nu = 128 B/node
+        p15 = capi.Params(nx=n, ny=n, nz=n, lattice=capi.LBM_D3Q15, storage=capi.LBM_F32,
+                          s=rates15(0.51) + [0.0] * 4, visc_kind=capi.LBM_VISC_SMAGORINSKY,
+                          visc_strain=capi.LBM_STRAIN_YU, nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+        s15 = lbm.LBM(p15, lbm.rho_u_field(np.zeros((n, n, n)), u))
+        log(f"D3Q15 FP32 {n}^3 LES: {args.warmup} warmup + {args.steps} timed steps")
+        w15, k15, d15 = time_run(s15, args.steps, args.warmup)
+        s15.close()
+        del s15
+        torch.cuda.empty_cache()
+        extra["les256_d3q15"] = {"MLUPS": round(N * args.steps / w15 / 1e6, 1),
+                                 "ms_per_step": round(w15 / args.steps * 1e3, 4),
+                                 "kernel_ms": round(k15 * 1e3, 4), "bytes_per_node": 128,
+                                 "hbm_frac": round(128 * N / k15 / 1e9 / HBM_PEAK_GBS, 4),
+                                 "ke": d15["ke"], "nonfinite": d15["nonfinite"]}
         result["extra"] = extra
 
     if not args.no_extra:

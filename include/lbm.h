@@ -7,19 +7,22 @@
  *   - the He-Luo D3Q19 MRT model of Section 2 (Eqs. mrteq, edf, omega, HeLuoD3Q19, the
  *     matrix T, Eqs. meq, sD3Q15, sD3Q15meaning);
  *   - the Yu formula (Eq. LuoS) and the Chai formula (Eq. ChaiS) of Section 3;
- *   - the D2Q9 variant that Section 5.3 says the Chai formula covers, with the Yu-type
- *     D2Q9 formula obtained by the route of Section 5.4.
+ *   - the D2Q9 and D3Q15 variants that Section 5.3 says the Chai formula covers, with the
+ *     Yu-type formulas obtained by the route of Section 5.4 (the D2Q9 basis is the
+ *     Lallemand-Luo one, the D3Q15 basis the d'Humieres et al. 2002 one; the paper gives
+ *     neither).
  *
  * Conventions shared by every entry point
  *   - All arrays are structure-of-arrays, x fastest: element (c, z, y, x) of a field with
  *     C components sits at  c*N + (z*ny + y)*nx + x,  N = nx*ny*nz.
  *   - Populations are the deviations g_i = f_i - w_i rho0 (the delta-rho form of Eq. edf),
- *     i in the velocity order of Eq. HeLuoD3Q19 (D3Q19) or (0, E, N, W, S, NE, NW, SW, SE)
- *     (D2Q9). "Canonical" populations are the pre-collision g_i(x, n) of Eq. mrteq. The
+ *     i in the velocity order of Eq. HeLuoD3Q19 (D3Q19), (0, E, N, W, S, NE, NW, SW, SE)
+ *     (D2Q9), or (0, +x, -x, +y, -y, +z, -z, (+++), (---), (++-), (--+), (+-+), (-+-),
+ *     (-++), (+--)) (D3Q15). "Canonical" populations are the pre-collision g_i(x, n) of Eq. mrteq. The
  *     library keeps its own internal layout in the two state buffers; only
  *     lbm_get_populations / lbm_set_populations / lbm_init convert.
- *   - Strain fields hold 6 components (xx, yy, zz, xy, yz, xz) for D3Q19 and 3 components
- *     (xx, yy, xy) for D2Q9, of the strain of the pre-collision state.
+ *   - Strain fields hold 6 components (xx, yy, zz, xy, yz, xz) for D3Q19 and D3Q15 and 3
+ *     components (xx, yy, xy) for D2Q9, of the strain of the pre-collision state.
  *   - Lattice units: delta_x = delta_t = 1, c_s^2 = 1/3.
  *   - Every pointer argument named as a field is a DEVICE pointer, caller-owned, and must
  *     stay valid while the context uses it. Buffers must be 256-byte aligned. No entry
@@ -54,7 +57,7 @@ typedef enum {
   LBM_EUNSUPPORTED = -6  /* valid but not provided combination (e.g. D2Q9 adjoint) */
 } lbm_status;
 
-typedef enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 } lbm_lattice;
+typedef enum { LBM_D2Q9 = 9, LBM_D3Q15 = 15, LBM_D3Q19 = 19 } lbm_lattice;
 typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
 typedef enum { LBM_STRAIN_NONE = 0, LBM_STRAIN_YU = 1, LBM_STRAIN_CHAI = 2 } lbm_strain_kind;
 typedef enum {
@@ -67,8 +70,10 @@ typedef enum {
 /*
  * Model parameters.
  *  s[]        diagonal of Lambda-hat (Eq. sD3Q15): 19 entries for D3Q19, the first 9 for
- *             D2Q9 (rates of rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy). The s_nu slots
- *             (D3Q19: 9, 11, 13, 14, 15; D2Q9: 7, 8) must hold one value, the initial s_nu.
+ *             D2Q9 (rates of rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy), the first 15 for
+ *             D3Q15 (rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, p_ww, p_xy, p_yz,
+ *             p_xz, m_xyz). The s_nu slots (D3Q19: 9, 11, 13, 14, 15; D3Q15: 9..13;
+ *             D2Q9: 7, 8) must hold one value, the initial s_nu.
  *  omega_*    the free equilibrium coefficients of Eq. meq (paper: 3, -11/2, -1/2);
  *             D3Q19 only.
  *  visc_kind  LBM_VISC_CONST: s_nu fixed.  LBM_VISC_SMAGORINSKY: nu = nu0 + c_smag^2 |S|.
@@ -76,7 +81,7 @@ typedef enum {
  *             nu = nu_max (n_pl < 1) or nu_min (n_pl > 1) at |S| = 0. |S| = sqrt(2 S:S).
  *             s_nu = 1/(3 nu + 1/2) relaxes the collision; the strain of the next step
  *             uses the s_nu of the previous collision at the node (held in s_nu_field).
- *             LBM_VISC_SMAGORINSKY_IMPLICIT (D3Q19): no lagged field; every node solves
+ *             LBM_VISC_SMAGORINSKY_IMPLICIT (D3Q19 only): no lagged field; every node solves
  *             s_nu = 1/(3 (nu0 + c_smag^2 |S(s_nu)|) + 1/2), S(s_nu) being the strain formula
  *             (affine in s_nu) at the rate of this very collision; s_nu_field may be NULL.
  *  visc_strain which formula drives the viscosity (LBM_STRAIN_YU or LBM_STRAIN_CHAI).
@@ -113,8 +118,9 @@ size_t lbm_population_bytes(const lbm_params* p);
  *               (the delta-rho form of Eq. edf).
  *  grad_u       device float[9*N], plane a*3+b = d u_b / d x_a, or NULL. When given, the
  *               non-equilibrium moments predicted by Eq. YuLuobasis are added (D3Q19: rows
- *               1, 9, 11, 13, 14, 15; D2Q9: rows 1, 7, 8), so the strain of the initial
- *               state equals the symmetric part of grad_u.
+ *               1, 9, 11, 13, 14, 15; D2Q9: rows 1, 7, 8; D3Q15: rows 1, 9..13, the
+ *               inverse of its Yu-type formula), so the strain of the initial state equals
+ *               the symmetric part of grad_u.
  * Errors: LBM_EINVAL (bad sizes, alignment, aliasing, unequal s_nu slots), LBM_ENOMEM,
  * LBM_EHIP. On error *out is NULL.
  */
@@ -124,7 +130,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
 /*
  * Advance nsteps steps of Eq. mrteq (collide with moment-space relaxation, Eq. mrteqvT,
  * then pull streaming), one fused kernel per step.
- *  S_out        device float[6*N] (D3Q19) / [3*N] (D2Q9) or NULL: receives, at every step,
+ *  S_out        device float[6*N] (D3Q19, D3Q15) / [3*N] (D2Q9) or NULL: receives, at every step,
  *               the strain (formula `strain_kind`) of that step's pre-collision state; after
  *               the call it holds the strain of the state at level n_end - 1.
  *  strain_kind  LBM_STRAIN_YU or LBM_STRAIN_CHAI (ignored when S_out is NULL).

@@ -24,7 +24,7 @@ _lib = ctypes.CDLL(str(_LIB_PATH))
 
 # enums (include/lbm.h)
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOMEM, LBM_ESTATE, LBM_ENONFINITE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-LBM_D2Q9, LBM_D3Q19 = 9, 19
+LBM_D2Q9, LBM_D3Q15, LBM_D3Q19 = 9, 15, 19
 LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
 LBM_STRAIN_NONE, LBM_STRAIN_YU, LBM_STRAIN_CHAI = 0, 1, 2
 LBM_VISC_CONST, LBM_VISC_SMAGORINSKY, LBM_VISC_POWERLAW, LBM_VISC_SMAGORINSKY_IMPLICIT = 0, 1, 2, 3

@@ -13,6 +13,7 @@
 #include <string>
 
 #include "internal.h"
+#include "launch.h"
 
 using namespace lbm;
 
@@ -60,7 +61,8 @@ size_t elem_size(int storage) {
 // Validate the parameters; on success fill Q and N.
 lbm_status check_params(const lbm_params* p, int* Q, size_t* N) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
-  if (p->lattice != LBM_D3Q19 && p->lattice != LBM_D2Q9) return fail(LBM_EINVAL, "lattice must be LBM_D3Q19 or LBM_D2Q9");
+  if (p->lattice != LBM_D3Q19 && p->lattice != LBM_D3Q15 && p->lattice != LBM_D2Q9)
+    return fail(LBM_EINVAL, "lattice must be LBM_D3Q19, LBM_D3Q15 or LBM_D2Q9");
   if (elem_size(p->storage) == 0) return fail(LBM_EINVAL, "storage must be LBM_F32, LBM_F16 or LBM_BF16");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 requires nz == 1");
@@ -74,10 +76,14 @@ lbm_status check_params(const lbm_params* p, int* Q, size_t* N) {
     const double sn = p->s[9];
     if (p->s[11] != sn || p->s[13] != sn || p->s[14] != sn || p->s[15] != sn)
       return fail(LBM_EINVAL, "D3Q19: the s_nu slots 9, 11, 13, 14, 15 must be equal");
+  } else if (q == 15) {
+    const double sn = p->s[9];
+    if (p->s[10] != sn || p->s[11] != sn || p->s[12] != sn || p->s[13] != sn)
+      return fail(LBM_EINVAL, "D3Q15: the s_nu slots 9..13 must be equal");
   } else {
     if (p->s[8] != p->s[7]) return fail(LBM_EINVAL, "D2Q9: the s_nu slots 7 and 8 must be equal");
   }
-  const int snu_slot = (q == 19) ? 9 : 7;
+  const int snu_slot = (q == 9) ? 7 : 9;
   if (!(p->s[snu_slot] > 0.0)) return fail(LBM_EINVAL, "s_nu must be positive");
   if (p->visc_kind < LBM_VISC_CONST || p->visc_kind > LBM_VISC_SMAGORINSKY_IMPLICIT)
     return fail(LBM_EINVAL, "bad visc_kind");
@@ -128,7 +134,8 @@ void fill_model(lbm_ctx* c) {
   else c->F.mode = 0;
 }
 
-bool is3d(const lbm_ctx* c) { return c->Q == 19; }
+// The adjoint and its per-step record are provided for D3Q19.
+bool is_d3q19(const lbm_ctx* c) { return c->Q == 19; }
 
 lbm_status check_ctx(const lbm_ctx* c) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
@@ -199,8 +206,11 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
     return fail(LBM_ENOMEM, std::string("hipMalloc of the reduction scratch failed: ") + hipGetErrorString(e));
   }
   const hipStream_t s = as_stream(stream);
-  e = is3d(c) ? d3q19::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s)
-              : d2q9::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s);
+  switch (c->Q) {
+    case 19: e = d3q19::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s); break;
+    case 15: e = d3q15::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s); break;
+    default: e = d2q9::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s); break;
+  }
   if (e != hipSuccess) {
     (void)hipFree(c->scratch);
     delete c;
@@ -210,9 +220,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
   return LBM_OK;
 }
 
-int lbm_save_planes(const lbm_ctx* c) { return (c && is3d(c)) ? save_planes(c->V) : 0; }
+int lbm_save_planes(const lbm_ctx* c) { return (c && is_d3q19(c)) ? save_planes(c->V) : 0; }
 
-int lbm_adjoint_planes(const lbm_ctx* c) { return (c && is3d(c)) ? adjoint_planes(c) : 0; }
+int lbm_adjoint_planes(const lbm_ctx* c) { return (c && is_d3q19(c)) ? adjoint_planes(c) : 0; }
 
 lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float* save, void* stream) {
   lbm_status st = check_ctx(c);
@@ -222,8 +232,8 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
   if (S_out && strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
   if (save && !aligned(save, 4)) return fail(LBM_EINVAL, "save must be 4-byte aligned");
-  if (save && !is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 only");
-  const size_t rec_elems = static_cast<size_t>(is3d(c) ? save_planes(c->V) : 0) * c->G.N;
+  if (save && !is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 only");
+  const size_t rec_elems = static_cast<size_t>(is_d3q19(c) ? save_planes(c->V) : 0) * c->G.N;
   const hipStream_t s = as_stream(stream);
   for (int n = 0; n < nsteps; ++n) {
     StepIO io;
@@ -233,8 +243,12 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
     io.S_out = S_out;
     io.emit = S_out ? strain_kind : 0;
     io.save = save ? save + static_cast<size_t>(n) * rec_elems : nullptr;
-    hipError_t e = is3d(c) ? d3q19::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s)
-                           : d2q9::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s);
+    hipError_t e;
+    switch (c->Q) {
+      case 19: e = d3q19::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s); break;
+      case 15: e = d3q15::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s); break;
+      default: e = d2q9::launch_step(c->p.storage, c->G, c->M, c->V, c->F, io, s); break;
+    }
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
     c->cur = 1 - c->cur;
     c->step += 1;
@@ -249,8 +263,12 @@ lbm_status lbm_strain(lbm_ctx* c, int strain_kind, float* S_out, void* stream) {
   if (strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
   const hipStream_t s = as_stream(stream);
-  hipError_t e = is3d(c) ? d3q19::launch_strain(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s)
-                         : d2q9::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s);
+  hipError_t e;
+  switch (c->Q) {
+    case 19: e = d3q19::launch_strain(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
+    case 15: e = d3q15::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
+    default: e = d2q9::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
+  }
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_strain");
 }
 
@@ -261,8 +279,12 @@ lbm_status lbm_reduce(lbm_ctx* c, double* host_out, void* stream) {
   const hipStream_t s = as_stream(stream);
   double* partials = c->scratch;
   double* dout = c->scratch + static_cast<size_t>(kReduceBlocks) * kReduceVals;
-  hipError_t e = is3d(c) ? d3q19::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s)
-                         : d2q9::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s);
+  hipError_t e;
+  switch (c->Q) {
+    case 19: e = d3q19::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
+    case 15: e = d3q15::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
+    default: e = d2q9::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
+  }
   if (e != hipSuccess) return hip_fail(e, "lbm_reduce");
   e = hipMemcpyAsync(host_out, dout, sizeof(double) * kReduceVals, hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(e, "lbm_reduce copy");
@@ -277,8 +299,12 @@ lbm_status lbm_get_populations(lbm_ctx* c, float* f_canon, void* stream) {
   if (st != LBM_OK) return st;
   if ((st = check_field(f_canon, "f_canon")) != LBM_OK) return st;
   const hipStream_t s = as_stream(stream);
-  hipError_t e = is3d(c) ? d3q19::launch_get(c->p.storage, c->G, c->buf[c->cur], f_canon, s)
-                         : d2q9::launch_get(c->p.storage, c->G, c->buf[c->cur], f_canon, s);
+  hipError_t e;
+  switch (c->Q) {
+    case 19: e = d3q19::launch_get(c->p.storage, c->G, c->buf[c->cur], f_canon, s); break;
+    case 15: e = d3q15::launch_get(c->p.storage, c->G, c->buf[c->cur], f_canon, s); break;
+    default: e = d2q9::launch_get(c->p.storage, c->G, c->buf[c->cur], f_canon, s); break;
+  }
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_get_populations");
 }
 
@@ -287,8 +313,12 @@ lbm_status lbm_set_populations(lbm_ctx* c, const float* f_canon, void* stream) {
   if (st != LBM_OK) return st;
   if ((st = check_field(f_canon, "f_canon")) != LBM_OK) return st;
   const hipStream_t s = as_stream(stream);
-  hipError_t e = is3d(c) ? d3q19::launch_set(c->p.storage, c->G, c->buf[c->cur], f_canon, s)
-                         : d2q9::launch_set(c->p.storage, c->G, c->buf[c->cur], f_canon, s);
+  hipError_t e;
+  switch (c->Q) {
+    case 19: e = d3q19::launch_set(c->p.storage, c->G, c->buf[c->cur], f_canon, s); break;
+    case 15: e = d3q15::launch_set(c->p.storage, c->G, c->buf[c->cur], f_canon, s); break;
+    default: e = d2q9::launch_set(c->p.storage, c->G, c->buf[c->cur], f_canon, s); break;
+  }
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_set_populations");
 }
 
@@ -333,7 +363,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const float* rec_n, const float* lam_in,
                             void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
   if ((st = check_field(rec_n, "rec_n")) != LBM_OK) return st;
   if ((st = check_field(lam_in, "lam_in")) != LBM_OK) return st;
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
@@ -351,7 +381,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const float* rec_n, const float* lam_in,
 lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, double* J_host, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
   if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
   if (!J_host) return fail(LBM_EINVAL, "J_host is NULL");
@@ -373,7 +403,7 @@ lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, d
 lbm_status lbm_init_adjoint(lbm_ctx* c, const float* rho_u, const float* lam0, float* grad_u0, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!is3d(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
   if ((st = check_field(rho_u, "rho_u")) != LBM_OK) return st;
   if ((st = check_field(lam0, "lam0")) != LBM_OK) return st;
   if ((st = check_field(grad_u0, "grad_u0")) != LBM_OK) return st;

@@ -5,6 +5,7 @@
 
 #include "d2q9.h"
 #include "internal.h"
+#include "launch.h"
 #include "reduce.h"
 
 namespace lbm {

@@ -12,6 +12,7 @@
 
 #include "d3q19.h"
 #include "internal.h"
+#include "launch.h"
 #include "reduce.h"
 
 namespace lbm {

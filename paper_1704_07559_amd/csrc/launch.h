@@ -1,0 +1,58 @@
+// Host-side launchers of the kernels (one translation unit per lattice), called by the C
+// ABI. Declarations only: nothing here changes the code of a kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace lbm {
+
+namespace d3q19 {
+hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float* snu, const float* rho_u,
+                       const float* grad_u, hipStream_t);
+hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
+                       hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, int kind, float* S_out, hipStream_t);
+hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
+hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, double* partials, double* out, hipStream_t);
+hipError_t launch_adjoint_step(const Geo&, const ModelF&, const ViscF&, const ForceF&, const float* rec,
+                               const float* lam_in, float* lam_out, float* grad_force, hipStream_t);
+hipError_t launch_loss_seed(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                            const float* snu, float* lam_out, float* grad_force, double* partials, double* out,
+                            hipStream_t);
+hipError_t launch_init_adjoint(const Geo&, const ModelF&, const float* rho_u, const float* lam0, float* grad_u0,
+                               hipStream_t);
+}  // namespace d3q19
+
+namespace d2q9 {
+hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float* snu, const float* rho_u,
+                       const float* grad_u, hipStream_t);
+hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
+                       hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         int kind, float* S_out, hipStream_t);
+hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
+hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         double* partials, double* out, hipStream_t);
+}  // namespace d2q9
+
+namespace d3q15 {
+hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float* snu, const float* rho_u,
+                       const float* grad_u, hipStream_t);
+hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
+                       hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         int kind, float* S_out, hipStream_t);
+hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
+hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
+                         double* partials, double* out, hipStream_t);
+}  // namespace d3q15
+
+hipError_t launch_reduce_final(const double* partials, int nblocks, double* out, hipStream_t);
+
+}  // namespace lbm

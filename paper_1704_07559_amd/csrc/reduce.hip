@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "launch.h"
 #include "reduce.h"
 
 namespace lbm {

@@ -54,7 +54,7 @@ class LBM:
 
     @property
     def ncomp(self) -> int:
-        return 6 if self.params.lattice == capi.LBM_D3Q19 else 3
+        return 3 if self.params.lattice == capi.LBM_D2Q9 else 6
 
     def step(self, nsteps: int = 1, S_out: Optional[torch.Tensor] = None, strain_kind: int = capi.LBM_STRAIN_YU,
              save: Optional[torch.Tensor] = None):
