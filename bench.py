@@ -91,16 +91,21 @@ def les_params(capi, n, storage):
                        nu0=(tau0 - 0.5) / 3.0, c_smag=0.1)
 
 
-def time_run(sim, steps, warmup, reduce_every=100):
-    """Run warmup + timed steps; returns (wall seconds, mean kernel seconds, last diagnostics)."""
+def time_run(sim, steps, warmup, reduce_every=100, windows=None):
+    """Run warmup + timed steps; returns (wall seconds, mean kernel seconds, last diagnostics).
+    With ``windows`` = a list, it also receives the device time per step (ms) of each run of
+    ``reduce_every`` steps (events at the window edges, on the launch stream)."""
     import torch
     sim.step(warmup)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    edges = []
     diag = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
+        if k % reduce_every == 0:
+            edges.append(ev[k][0])
         ev[k][0].record()
         sim.step(1)
         ev[k][1].record()
@@ -109,6 +114,9 @@ def time_run(sim, steps, warmup, reduce_every=100):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern = sum(a.elapsed_time(b) for a, b in ev) / steps / 1e3
+    if windows is not None:
+        for a, b in zip(edges[:-1], edges[1:]):
+            windows.append(a.elapsed_time(b) / reduce_every)
     if diag is None:
         diag = sim.reduce(allow_nonfinite=True)
     return wall, kern, diag
@@ -215,15 +223,27 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50
             "grad_u0_norm": float(u0.grad.norm()), "grad_F_norm": float(F.grad.norm())}
 
 
-def cpu_baseline(u_full, n_slab=64, steps=6):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(u_full, n_slab=64, steps=6, steps_1t=2):
     """FP64 oracle on a 256 x 256 x n_slab z-slab of the same initial field (periodic in the
-    slab), Smagorinsky from Yu, ``steps`` steps."""
+    slab), Smagorinsky from Yu: ``steps`` steps with the BLAS thread pool as configured, then
+    ``steps_1t`` steps with one thread."""
     import numpy as np
     from oracle import d3q19 as od
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     u = np.ascontiguousarray(u_full[:, :n_slab])
     shape = u.shape[1:]
@@ -235,9 +255,16 @@ def cpu_baseline(u_full, n_slab=64, steps=6):
     sim.step(steps)
     dt = time.perf_counter() - t0
     nodes = int(np.prod(shape))
-    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 NumPy oracle, {shape[2]}x{shape[1]}x{shape[0]} z-slab of the 256^3 workload, "
-                      f"{steps} steps, {dt:.1f} s"}
+    out = {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 NumPy oracle, {shape[2]}x{shape[1]}x{shape[0]} z-slab of the 256^3 workload, "
+                     f"{steps} steps, {dt:.1f} s", "cpu_model": _cpu_model()}
+    if threadpool_limits is not None and steps_1t > 0:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            sim.step(steps_1t)
+            dt1 = time.perf_counter() - t0
+        out["single_thread_value"] = nodes * steps_1t / dt1 / 1e6
+    return out
 
 
 def main():
@@ -284,7 +311,8 @@ def main():
     del rho_u
     N = n ** 3
     log(f"FP32 {n}^3: {args.warmup} warmup + {args.steps} timed steps")
-    wall, kern, diag = time_run(sim, args.steps, args.warmup)
+    win = []
+    wall, kern, diag = time_run(sim, args.steps, args.warmup, windows=win)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -317,6 +345,11 @@ def main():
                      "kernel_source_sha": sha},
         "diagnostics": {"mass": diag["mass"], "ke": diag["ke"], "umax": diag["umax"], "nonfinite": diag["nonfinite"]},
     }
+    if win:
+        # device time of consecutive 100-step windows (each includes its diagnostics reduction)
+        wm = sorted(N / (w * 1e-3) / 1e6 for w in win)
+        result["windows_MLUPS"] = {"count": len(wm), "min": round(wm[0], 1), "median": round(wm[len(wm) // 2], 1),
+                                   "max": round(wm[-1], 1)}
 
     if not args.no_extra:
         extra = {}

@@ -80,15 +80,17 @@ def sample_nodes(shape, count, seed):
     return sorted(nodes)
 
 
-def patch_reference(make_params, u, node, k, walls, force=None):
+def patch_reference(make_params, u, node, k, walls, force=None, oracle=None):
     """FP64 oracle values at one node after k steps, from the radius-k neighbourhood of the
     initial field only (the value of a node after k steps depends on no other node).
 
     Periodic axes wrap; with y-walls the rows are clipped at the walls and the patch streams
     with bounce-back (a wrong edge at an interior cut cannot reach the centre in k steps).
     Returns (g after k steps at the node, Yu strain of every step's pre-collision state at
-    the node, s_nu after k steps at the node)."""
-    from oracle import d3q19 as od
+    the node, s_nu after k steps at the node). ``oracle``: the lattice's oracle module
+    (default D3Q19)."""
+    from oracle import d3q19
+    od = oracle or d3q19
     _, nz, ny, nx = u.shape
     z, y, x = node
     zs = [(z + d) % nz for d in range(-k, k + 1)]
@@ -110,5 +112,6 @@ def patch_reference(make_params, u, node, k, walls, force=None):
     strains = []
     for _ in range(k):
         out = sim.step(1)
-        strains.append(out.S_yu[:, cz, cy, cx].copy())
+        S_yu = out.S_yu if hasattr(out, "S_yu") else out[0]
+        strains.append(S_yu[:, cz, cy, cx].copy())
     return sim.g[:, cz, cy, cx].copy(), strains, float(sim.s_nu[cz, cy, cx])

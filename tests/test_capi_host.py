@@ -44,6 +44,26 @@ def test_population_bytes_and_validation():
     assert capi.lbm_population_bytes(capi.Params(nx=4, ny=4, nz=2, lattice=capi.LBM_D2Q9, s=s)) == 0
 
 
+def test_size_limits_and_other_lattices():
+    """32-bit plane offsets: N must stay below 2^30 nodes; D3Q15 sizing and its s_nu slots;
+    the implicit coupling only on D3Q19."""
+    from paper_1704_07559_amd import capi
+    s = [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, 1.25, 1.4, 1.25, 1.4, 1.25, 1.25, 1.25, 1.98, 1.98, 1.98]
+    assert capi.lbm_population_bytes(capi.Params(nx=1024, ny=1024, nz=1023, s=s)) == 19 * 4 * 1024 * 1024 * 1023
+    assert capi.lbm_population_bytes(capi.Params(nx=1024, ny=1024, nz=1024, s=s)) == 0
+    assert capi.lbm_population_bytes(capi.Params(nx=1, ny=1, nz=1, s=s)) == 19 * 4
+    s15 = [0.0, 1.6, 1.2, 0.0, 1.6, 0.0, 1.6, 0.0, 1.6, 1.25, 1.25, 1.25, 1.25, 1.25, 1.2] + [0.0] * 4
+    assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=capi.LBM_D3Q15, s=s15)) == 15 * 4 * 120
+    uneq = list(s15)
+    uneq[12] = 1.3
+    assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=capi.LBM_D3Q15, s=uneq)) == 0
+    imp = capi.LBM_VISC_SMAGORINSKY_IMPLICIT
+    assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=capi.LBM_D3Q15, s=s15,
+                                                 visc_kind=imp)) == 0
+    assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, s=s, visc_kind=imp)) == 19 * 4 * 120
+    assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=7, s=s)) == 0
+
+
 def test_init_rejects_bad_arguments_without_a_gpu():
     """Every case here fails validation, which runs before any HIP call or launch."""
     from paper_1704_07559_amd import capi

@@ -130,3 +130,51 @@ def test_half_precision_storage_against_oracle(storage, tol):
     ref.step(20)
     assert strain_rel_err(to_np(sim.strain(capi.LBM_STRAIN_YU)), ref.strain("yu")) < tol
     sim.close()
+
+
+@pytest.mark.slow
+def test_les_256_cubed_d3q15_sampled():
+    """The D3Q15 LES workload bench.py times (256^3, FP32, Smagorinsky C_s = 0.1 from the
+    Yu-type strain, tau_nu0 = 0.51), in that launch configuration: two steps, then the
+    populations and both strains at sampled nodes against the FP64 oracle run on each node's
+    neighbourhood, Yu-type = Chai over the whole field, mass conservation."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    from tests._common import patch_reference, sample_nodes
+    n, K = 256, 2
+    shape = (n, n, n)
+    u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
+    kw = dict(visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    op, cp = _spec(shape, tau=0.51, **kw)
+    sim = lbm.LBM(cp, lbm.rho_u_field(np.zeros(shape), u))
+    m0 = sim.reduce()["mass"]
+    S = [torch.empty((6,) + shape, device="cuda") for _ in range(K)]
+    for k in range(K):
+        sim.step(1, S_out=S[k], strain_kind=capi.LBM_STRAIN_YU)
+    Sy, Sc = sim.strain(capi.LBM_STRAIN_YU), sim.strain(capi.LBM_STRAIN_CHAI)
+    frob = torch.sqrt((Sy[:3] ** 2).sum(0) + 2 * (Sy[3:] ** 2).sum(0)).max().item()
+    assert (Sy - Sc).abs().max().item() < 1e-4 * frob   # two FP32 evaluations of one quantity
+    g = sim.populations()
+    nodes = sample_nodes(shape, 24, 7)
+    idx = tuple(torch.tensor(a, device="cuda") for a in zip(*nodes))
+    g_s = g[(slice(None),) + idx].double().cpu().numpy()
+    S_s = [s[(slice(None),) + idx].double().cpu().numpy() for s in S]
+    d = sim.reduce()
+    sim.close()
+
+    def make_params(Fp):
+        q = od.Params(**{f: getattr(op, f) for f in op.__dataclass_fields__})
+        q.force = Fp
+        return q
+
+    worst_g, dS, fr = 0.0, 0.0, 0.0
+    wts = np.array([1, 1, 1, 2, 2, 2])
+    for m, node in enumerate(nodes):
+        g_ref, S_ref, _ = patch_reference(make_params, u, node, K, False, None, oracle=od)
+        f_ref = g_ref + od.W
+        worst_g = max(worst_g, float(np.max(np.abs(g_s[:, m] + od.W - f_ref) / np.abs(f_ref))))
+        for k in range(K):
+            dS = max(dS, float(np.abs(S_s[k][:, m] - S_ref[k]).max()))
+            fr = max(fr, float(np.sqrt((wts * S_ref[k] ** 2).sum())))
+    assert worst_g < 1e-5 and dS / fr < 1e-4, (worst_g, dS / fr)
+    assert d["nonfinite"] == 0 and abs(d["mass"] - m0) < 1e-3

@@ -103,3 +103,32 @@ def test_les_384_cubed_fp16_sampled():
     # half-ulps per step on f
     assert wg < 4 * 2.0 ** -11, wg
     assert diag["nonfinite"] == 0
+
+
+@pytest.mark.slow
+def test_channel_128x128x512_newtonian_startup_5000_steps():
+    """The channel configuration with n = 1 (constant nu = K = 0.1 from the Chai-driven power
+    law), from rest, 5000 steps: the velocity profile follows the start-up series of plane
+    Poiseuille flow (a property at any size), and is uniform in x and z."""
+    import torch
+    from oracle import closed_forms as cf
+    from paper_1704_07559_amd import lbm
+    shape = (512, 128, 128)
+    F = 1e-6
+    _, cp, _ = spec_params(shape, tau=0.8, visc="powerlaw", drive="chai", K_pl=0.1, n_pl=1.0, nu_min=1e-3,
+                           nu_max=1.0, walls=True, force=np.array([0.0, 0.0, F]))
+    sim = lbm.LBM(cp)
+    steps = 5000
+    sim.step(steps)
+    g = sim.populations()
+    cz = torch.as_tensor(od.C[2].astype(np.float32), device="cuda")
+    uz = ((cz[:, None, None, None] * g).sum(0) + 0.5 * F) / cp.rho0          # (nz, ny, nx)
+    prof = uz.mean(dim=(0, 2)).double().cpu().numpy()
+    spread = (uz - uz.mean(dim=(0, 2), keepdim=True)).abs().max().item()
+    d = sim.reduce()
+    sim.close()
+    eta = np.arange(128) + 0.5
+    ref = cf.startup_poiseuille(eta, 128, F, 0.1, steps)
+    assert np.abs(prof - ref).max() < 0.01 * np.abs(ref).max()
+    assert spread < 1e-6 * np.abs(ref).max()
+    assert d["nonfinite"] == 0

@@ -72,7 +72,9 @@ def test_storage_error_against_fp64_oracle_64_cubed():
 @pytest.mark.slow
 def test_storage_error_against_fp32_run_384_cubed():
     """The 384^3 storage configuration: FP16 and BF16 runs against the FP32-stored run at
-    steps 10, 100 and 1000 (pointwise populations and strain, kinetic energy)."""
+    steps 10, 100 and 1000: pointwise populations and strain, kinetic energy, the
+    dissipation proxy sum S:S and the shell-summed energy spectrum (errors stated, not
+    pinned: no reference value exists)."""
     import torch
     from paper_1704_07559_amd import capi, lbm
     n = 384
@@ -82,6 +84,27 @@ def test_storage_error_against_fp32_run_384_cubed():
     del u
     marks = (10, 100, 1000)
     runs = {}
+    cvec = torch.as_tensor(od.C.astype(np.float32), device="cuda")          # (3, 19)
+    kk = torch.fft.fftfreq(n, d=1.0 / n, device="cuda")
+    kr = torch.fft.rfftfreq(n, d=1.0 / n, device="cuda")
+    kmag = torch.sqrt(kk[:, None, None] ** 2 + kk[None, :, None] ** 2 + kr[None, None, :] ** 2)
+    shell = torch.round(kmag).long().reshape(-1)
+    # rfft keeps half of the k_x axis: the interior planes stand for two modes each
+    mult = torch.full((n // 2 + 1,), 2.0, device="cuda")
+    mult[0] = 1.0
+    mult[-1] = 1.0
+    mult = mult[None, None, :].expand(n, n, n // 2 + 1).reshape(-1)
+
+    def spectrum(g):
+        """Shell-summed kinetic energy spectrum E(k) of u = j / rho0 (test-side analysis)."""
+        u = (cvec @ g.reshape(19, -1)).reshape(3, n, n, n)
+        E = torch.zeros(n, device="cuda", dtype=torch.float64)
+        for a in range(3):
+            uh = torch.fft.rfftn(u[a]) / n**3
+            e = (0.5 * (uh.real**2 + uh.imag**2)).reshape(-1).double() * mult
+            E += torch.bincount(shell, weights=e, minlength=n)[:n]
+        return E[: n // 2 + 1]
+
     for storage in ("f32", "f16", "bf16"):
         _, cp, _ = spec_params(shape, storage=storage, **LES)
         sim = lbm.LBM(cp, rho_u)
@@ -90,21 +113,31 @@ def test_storage_error_against_fp32_run_384_cubed():
             sim.step(m - done)
             done = m
             d = sim.reduce()
-            runs[(storage, m)] = (sim.populations(),
-                                  sim.strain(capi.LBM_STRAIN_YU), d)
+            g = sim.populations()
+            runs[(storage, m)] = (g, sim.strain(capi.LBM_STRAIN_YU), d, spectrum(g))
         sim.close()
         torch.cuda.empty_cache()
     out = {}
     w = torch.as_tensor(od.W, dtype=torch.float32, device="cuda").reshape(19, 1, 1, 1)
     for st in ("f16", "bf16"):
         for m in marks:
-            g32, S32, d32 = runs[("f32", m)]
-            g, S, d = runs[(st, m)]
+            g32, S32, d32, E32 = runs[("f32", m)]
+            g, S, d, E = runs[(st, m)]
             f32 = g32 + w
             pop = ((g.float() + w - f32).abs() / f32.abs()).max().item()
             frob = torch.sqrt((S32[:3] ** 2).sum(0) + 2 * (S32[3:] ** 2).sum(0)).max().item()
+            # the initial spectrum has no energy beyond k ~ 20: relative errors are taken where
+            # E32 holds at least 1e-3 of the peak, absolute ones against the peak everywhere
+            energetic = (E32 >= 1e-3 * E32.max())
+            energetic[0] = False
+            spec_rel = ((E - E32).abs() / E32)[energetic].max().item()
+            spec_abs = ((E - E32).abs() / E32.max())[1:].max().item()
             out[f"{st}_step{m}"] = {"pop_rel_vs_f32": pop, "strain_rel_vs_f32": (S - S32).abs().max().item() / frob,
                                      "ke_rel_vs_f32": abs(d["ke"] - d32["ke"]) / d32["ke"],
+                                     "dissipation_rel_vs_f32": abs(d["ss"] - d32["ss"]) / d32["ss"],
+                                     "spectrum_rel_vs_f32_energetic_k": spec_rel,
+                                     "spectrum_abs_vs_f32_over_peak": spec_abs,
+                                     "energetic_k_max": int(torch.nonzero(energetic).max().item()),
                                      "nonfinite": d["nonfinite"]}
     _record("storage_errors_384.json", out)
     for st, eps in (("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
@@ -112,3 +145,4 @@ def test_storage_error_against_fp32_run_384_cubed():
             e = out[f"{st}_step{m}"]
             assert e["nonfinite"] == 0
             assert e["ke_rel_vs_f32"] < 500 * eps, (st, m, e)
+            assert np.isfinite(e["dissipation_rel_vs_f32"]) and np.isfinite(e["spectrum_rel_vs_f32_energetic_k"])
