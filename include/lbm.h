@@ -199,6 +199,17 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const float* rec_n, const float* lam_i
                             float* grad_force, void* stream);
 
 /*
+ * nsteps reverse steps in one call: for n = nsteps-1 down to 0, lbm_adjoint_step with the
+ * record rec + n*R*N (R = lbm_save_planes(ctx), as one lbm_step(nsteps, ..., save) call
+ * wrote them), the adjoint state ping-ponging between lam_a and lam_b (each device
+ * float[lbm_adjoint_planes(ctx)*N], not overlapping). On entry lam_a holds the adjoint after
+ * the last step; on return lam_a holds the adjoint before the first (lam_b is scratch).
+ * grad_force as in lbm_adjoint_step. Saves a host round trip per step.
+ */
+lbm_status lbm_adjoint_steps(lbm_ctx* ctx, int nsteps, const float* rec, float* lam_a, float* lam_b,
+                             float* grad_force, void* stream);
+
+/*
  * Loss J = sum_x S:S of the current pre-collision state (Yu formula, which equals Chai,
  * Section 5.1, at the rate the viscosity model gives the state: s_nu of the parameters, the
  * lagged field, or the implicitly solved rate), its gradient into lam_out (device

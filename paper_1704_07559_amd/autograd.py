@@ -9,9 +9,9 @@ Smagorinsky or power law, implicit Smagorinsky). ``backward`` runs the hand-writ
 kernels of the library: the forward sweep stores the state (populations and, for the lagged
 models, the s_nu field) every ``every`` steps; the reverse sweep reloads each checkpoint,
 recomputes its segment saving the per-step adjoint record (3 floats per node for a constant
-viscosity: j; 10 for a strain-dependent one), then applies lbm_adjoint_step backwards through
-the segment; lbm_init_adjoint maps the last adjoint state onto u0. Peak extra memory:
-ceil(N/every) states plus ``every`` records.
+viscosity: j; 10 for a strain-dependent one), then runs the adjoint steps backwards through
+the segment in one lbm_adjoint_steps call; lbm_init_adjoint maps the last adjoint state onto
+u0. Peak extra memory: ceil(N/every) states plus ``every`` records.
 """
 from __future__ import annotations
 
@@ -63,9 +63,7 @@ class StrainLoss(torch.autograd.Function):
             k = min(prob.every, prob.nsteps - n0)
             sim.load_state(ctx.checkpoints[seg])
             sim.step(k, save=rec)
-            for n in reversed(range(k)):
-                capi.lbm_adjoint_step(sim.ctx, rec[n], lam, lam2, gF)
-                lam, lam2 = lam2, lam
+            capi.lbm_adjoint_steps(sim.ctx, k, rec, lam, lam2, gF)
         gu = torch.empty((3, N), dtype=torch.float32, device=lam.device)
         capi.lbm_init_adjoint(sim.ctx, ctx.rho_u, lam, gu)
         scale = gJ.to(torch.float32)

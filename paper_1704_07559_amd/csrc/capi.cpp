@@ -378,6 +378,40 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const float* rec_n, const float* lam_in,
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_step");
 }
 
+lbm_status lbm_adjoint_steps(lbm_ctx* c, int nsteps, const float* rec, float* lam_a, float* lam_b, float* grad_force,
+                             void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  if ((st = check_field(rec, "rec")) != LBM_OK) return st;
+  if ((st = check_field(lam_a, "lam_a")) != LBM_OK) return st;
+  if ((st = check_field(lam_b, "lam_b")) != LBM_OK) return st;
+  if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
+  const size_t lam_bytes = sizeof(float) * adjoint_planes(c) * static_cast<size_t>(c->G.N);
+  {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(lam_a), b = reinterpret_cast<uintptr_t>(lam_b);
+    if ((a < b ? b - a : a - b) < lam_bytes) return fail(LBM_EINVAL, "lam_a and lam_b overlap");
+  }
+  const hipStream_t s = as_stream(stream);
+  const size_t rec_elems = static_cast<size_t>(save_planes(c->V)) * c->G.N;
+  float* in = lam_a;
+  float* out = lam_b;
+  for (int n = nsteps - 1; n >= 0; --n) {
+    hipError_t e = d3q19::launch_adjoint_step(c->G, c->M, c->V, c->F, rec + static_cast<size_t>(n) * rec_elems, in,
+                                              out, grad_force, s);
+    if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps");
+    float* t = in;
+    in = out;
+    out = t;
+  }
+  if (in != lam_a) {
+    hipError_t e = hipMemcpyAsync(lam_a, in, lam_bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps copy");
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, double* J_host, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;

@@ -140,3 +140,29 @@ def test_record_planes_and_validation():
     sim2 = lbm.LBM(p2)
     assert (sim2.save_planes, sim2.adjoint_planes) == (0, 0)
     sim2.close()
+
+
+@pytest.mark.parametrize("name,nsteps", [("const", 5), ("const", 4), ("smag_yu", 3), ("implicit_chai", 6)])
+def test_adjoint_steps_equals_single_steps(name, nsteps):
+    """lbm_adjoint_steps (one call, lambda ping-pong inside the library) is bit-identical to
+    nsteps lbm_adjoint_step calls, for odd and even nsteps; the result lands in lam_a."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape = (4, 9, 64)
+    F = _f32(synth.uniform_random_force(shape, seed=60, amp=1e-4))
+    kw = {} if name == "const" else MODELS[name]
+    op, cp, _ = spec_params(shape, tau=0.8, force=F, **kw)
+    u = synth.random_vector(shape, seed=61, scale=0.05)
+    sim = lbm.LBM(cp, lbm.rho_u_field(np.zeros(shape), u))
+    N, R, A = cp.N, sim.save_planes, sim.adjoint_planes
+    rec = torch.empty((nsteps, R, N), device="cuda")
+    sim.step(nsteps, save=rec)
+    lam0 = torch.as_tensor(synth.random_state(A, shape, seed=62, scale=1.0).astype(np.float32)).cuda().reshape(A, N)
+    a, b, gF = lam0.clone(), torch.empty_like(lam0), torch.zeros((3, N), device="cuda")
+    capi.lbm_adjoint_steps(sim.ctx, nsteps, rec, a, b, gF)
+    x, y, gF1 = lam0.clone(), torch.empty_like(lam0), torch.zeros((3, N), device="cuda")
+    for n in reversed(range(nsteps)):
+        capi.lbm_adjoint_step(sim.ctx, rec[n], x, y, gF1)
+        x, y = y, x
+    assert torch.equal(a, x) and torch.equal(gF, gF1)
+    sim.close()
