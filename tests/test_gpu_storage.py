@@ -4,10 +4,10 @@ GPU run (384^3), on the seeded LES recipe (k^4 exp(-2(k/4)^2) spectrum, seed 170
 u_rms = 0.04, Smagorinsky C_s = 0.1 from the Yu strain, tau_nu0 = 0.51).
 
 The FP32 rows meet the usual parity bar. For FP16 and BF16 no reference value exists;
-the measured errors are written to gpurun_out/storage_errors*.json (when that folder
-exists) and the asserted bounds are a small multiple of what the storage rounding
-predicts: a half-ulp of the stored deviation per step, 2^-11 (FP16) or 2^-8 (BF16)
-relative, accumulated over the steps.
+the measured errors are written to storage_errors*.json in the folder named by the
+environment variable LBM_RESULTS_DIR (when it is set), and the asserted bounds are a small
+multiple of what the storage rounding predicts: a half-ulp of the stored deviation per
+step, 2^-11 (FP16) or 2^-8 (BF16) relative, accumulated over the steps.
 """
 import json
 import os
@@ -26,8 +26,9 @@ LES = dict(tau=TAU0, visc="smagorinsky", drive="yu", nu0=(TAU0 - 0.5) / 3.0, c_s
 
 
 def _record(name, data):
-    if os.path.isdir("gpurun_out"):
-        with open(os.path.join("gpurun_out", name), "w") as f:
+    out = os.environ.get("LBM_RESULTS_DIR")
+    if out and os.path.isdir(out):
+        with open(os.path.join(out, name), "w") as f:
             json.dump(data, f, indent=1)
 
 
