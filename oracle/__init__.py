@@ -16,7 +16,11 @@ Modules
 d3q19        the D3Q19 model (Section 2), the Yu formula (Eq. LuoS), the Chai formula
              (Eq. ChaiS), the viscosity models, Guo forcing, bounce-back walls, the step
 d2q9         the D2Q9 variant (Section 5.3/5.4 generality; lattice from outside the paper)
-adjoint      discrete adjoint of the D3Q19 step and of the strain-squared loss
+d3q15        the D3Q15 variant (Section 5.3/5.4 generality; basis from outside the paper)
+adjoint      discrete adjoint of the D3Q19 step and of the strain-squared loss (constant
+             viscosity)
+adjoint_visc the same for strain-dependent viscosities (lagged Smagorinsky and power law,
+             implicit Smagorinsky)
 closed_forms exact Navier-Stokes solutions used as expected values (Taylor-Green,
              power-law Poiseuille, start-up Poiseuille series)
 naive        a per-node pure-Python loop of the step for brute-force checks on tiny grids
