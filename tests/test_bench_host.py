@@ -1,0 +1,33 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU contract, the traffic record lookup,
+the relaxation-rate tables."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_traffic_record_matches_only_its_kernel_source(tmp_path, monkeypatch):
+    sha = bench.kernel_source_sha()
+    assert len(sha) == 16
+    rec = bench.read_traffic("step_d3q19_f32_les256", sha)
+    assert rec is None or 150 * 256**3 < rec < 175 * 256**3      # bytes per launch, near 160 B/node
+    assert bench.read_traffic("step_d3q19_f32_les256", "0" * 16) is None
+    assert bench.read_traffic("no_such_kernel", sha) is None
+
+
+def test_rate_tables():
+    r19, r15 = bench.rates(0.5 + 1.0 / 3.0), bench.rates15(0.8)
+    assert len(r19) == 19 and len(r15) == 15
+    assert {r19[k] for k in (9, 11, 13, 14, 15)} == {1.0 / (0.5 + 1.0 / 3.0)}
+    assert {r15[k] for k in range(9, 14)} == {1.0 / 0.8}
+    assert r19[0] == r19[3] == r19[5] == r19[7] == 0.0 and r15[0] == r15[3] == r15[5] == r15[7] == 0.0
