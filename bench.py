@@ -145,6 +145,60 @@ def channel_runs(torch, capi, lbm, steps, warmup):
     return out
 
 
+def _event_time(torch, fn, reps):
+    """Mean device time of fn() over reps calls (events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def other_kernels(torch, np, synth, capi, lbm, u, steps, warmup):
+    """The remaining kernels of the path, each against its algorithmic bytes per node:
+    the D3Q19 step emitting the Chai strain every step (160 + 24 B), the strain query
+    (76 + 4 + 24 B), the diagnostics reduction (76 + 4 B read) on the 256^3 LES state, and the
+    D2Q9 LES step on 4096^2 (9 x 4 x 2 + 8 = 80 B)."""
+    out = {}
+    n = u.shape[1]
+    N = n ** 3
+    sim = lbm.LBM(les_params(capi, n, capi.LBM_F32), lbm.rho_u_field(np.zeros((n, n, n)), u))
+    S = torch.empty((6, n, n, n), device="cuda")
+    sim.step(warmup)
+    t = _event_time(torch, lambda: sim.step(1, S_out=S, strain_kind=capi.LBM_STRAIN_CHAI), steps)
+    out["step_with_chai_strain_256"] = {"kernel_ms": round(t * 1e3, 4), "bytes_per_node": 184,
+                                        "hbm_frac": round(184 * N / t / 1e9 / HBM_PEAK_GBS, 4)}
+    t = _event_time(torch, lambda: capi.lbm_strain(sim.ctx, capi.LBM_STRAIN_YU, S), 50)
+    out["strain_query_256"] = {"kernel_ms": round(t * 1e3, 4), "bytes_per_node": 104,
+                               "hbm_frac": round(104 * N / t / 1e9 / HBM_PEAK_GBS, 4)}
+    t = _event_time(torch, lambda: sim.reduce(), 20)
+    out["diagnostics_reduce_256"] = {"call_ms": round(t * 1e3, 4), "bytes_per_node": 80,
+                                     "hbm_frac": round(80 * N / t / 1e9 / HBM_PEAK_GBS, 4),
+                                     "note": "includes the final pass and the host copy"}
+    sim.close()
+    del sim, S
+    torch.cuda.empty_cache()
+    m = 4096
+    u2 = synth.spectrum_velocity((1, m, m), seed=1704, u_rms=0.04)[:2]
+    sn = 1.0 / 0.51
+    p2 = capi.Params(nx=m, ny=m, nz=1, lattice=capi.LBM_D2Q9, s=[0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, sn, sn],
+                     visc_kind=capi.LBM_VISC_SMAGORINSKY, visc_strain=capi.LBM_STRAIN_YU,
+                     nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    s2 = lbm.LBM(p2, lbm.rho_u_field(np.zeros((1, m, m)), u2))
+    log(f"D2Q9 {m}^2 LES: {warmup} warmup + {steps} timed steps")
+    w2, k2, d2 = time_run(s2, steps, warmup)
+    s2.close()
+    torch.cuda.empty_cache()
+    out["d2q9_les_4096sq"] = {"MLUPS": round(m * m * steps / w2 / 1e6, 1), "kernel_ms": round(k2 * 1e3, 4),
+                              "bytes_per_node": 80, "hbm_frac": round(80 * m * m / k2 / 1e9 / HBM_PEAK_GBS, 4),
+                              "nonfinite": d2["nonfinite"]}
+    return out
+
+
 def copy_bandwidth(torch):
     """Plain device-to-device copy of 1 GiB (read + write), for context."""
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -413,6 +467,8 @@ def main():
         torch.cuda.empty_cache()
         result["extra"]["adjoint_c4_smagorinsky"] = adjoint_run(torch, np, synth, capi, lbm, args.warmup,
                                                                 visc="smagorinsky")
+        result["extra"]["other_kernels"] = other_kernels(torch, np, synth, capi, lbm, u, max(1, args.steps // 5),
+                                                         args.warmup)
         result["extra"]["copy_GBps"] = copy_bandwidth(torch)
 
     if not args.no_cpu_baseline:

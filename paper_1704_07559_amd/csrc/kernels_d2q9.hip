@@ -65,7 +65,8 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   }
   if (io.S_out) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) io.S_out[static_cast<size_t>(c) * G.N + self] = io.emit == 2 ? Sch[c] : Syu[c];
+    for (int c = 0; c < 3; ++c)
+      stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
   }
   float snu = M.s[7];
   if (V.kind != 0) {
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Forc
     strain_yu(noneq_moments(P, drho, jx, jy, M.inv_rho0), M.s[1], snu, M.inv_rho0, S3);
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) S_out[static_cast<size_t>(c) * G.N + nb.self] = S3[c];
+  for (int c = 0; c < 3; ++c) stream_store(&S_out[static_cast<size_t>(c) * G.N + nb.self], S3[c]);
 }
 
 template <typename S>

@@ -106,7 +106,8 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
         strain_yu(n, M.s[1], snu, M.inv_rho0, Syu);
       }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) io.S_out[static_cast<size_t>(c) * G.N + self] = io.emit == 2 ? Sch[c] : Syu[c];
+      for (int c = 0; c < 6; ++c)
+        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
     }
   } else {
     // lagged coupling: the strain of the incoming state with the rates of the previous collision
@@ -122,7 +123,8 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
     }
     if (io.S_out) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) io.S_out[static_cast<size_t>(c) * G.N + self] = io.emit == 2 ? Sch[c] : Syu[c];
+      for (int c = 0; c < 6; ++c)
+        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
     }
     // viscosity model -> s_nu of this collision (kept for the next step's strain)
     if (V.kind != 0) {
@@ -161,17 +163,17 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
     // what the adjoint of this step needs: j, and for a strain-dependent viscosity the
     // non-equilibrium moments entering Eq. LuoS and the rate the strain was taken with
     const size_t N = G.N;
-    io.save[self] = jx;
-    io.save[N + self] = jy;
-    io.save[2 * N + self] = jz;
+    stream_store(&io.save[self], jx);
+    stream_store(&io.save[N + self], jy);
+    stream_store(&io.save[2 * N + self], jz);
     if (V.kind != 0) {
-      io.save[3 * N + self] = n.m[1];
-      io.save[4 * N + self] = n.m[9];
-      io.save[5 * N + self] = n.m[11];
-      io.save[6 * N + self] = n.m[13];
-      io.save[7 * N + self] = n.m[14];
-      io.save[8 * N + self] = n.m[15];
-      io.save[9 * N + self] = s_strain;
+      stream_store(&io.save[3 * N + self], n.m[1]);
+      stream_store(&io.save[4 * N + self], n.m[9]);
+      stream_store(&io.save[5 * N + self], n.m[11]);
+      stream_store(&io.save[6 * N + self], n.m[13]);
+      stream_store(&io.save[7 * N + self], n.m[14]);
+      stream_store(&io.save[8 * N + self], n.m[15]);
+      stream_store(&io.save[9 * N + self], s_strain);
     }
   }
 }
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Visc
     strain_yu(n, M.s[1], snu, M.inv_rho0, S6);
   }
 #pragma unroll
-  for (int c = 0; c < 6; ++c) S_out[static_cast<size_t>(c) * G.N + nb.self] = S6[c];
+  for (int c = 0; c < 6; ++c) stream_store(&S_out[static_cast<size_t>(c) * G.N + nb.self], S6[c]);
 }
 
 // ------------------------------------------------------------------------------------------
