@@ -35,9 +35,9 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS & % HBM roofline, D3Q19 MRT+strain, FP32 vs FP16-stored; adjoint/fwd cost"
 # The sources the D3Q19 step kernel is compiled from (launch.h holds host-side
 # declarations only and is left out).
-KERNEL_SOURCES = ["paper_1704_07559_amd/csrc/kernels_d3q19.hip", "paper_1704_07559_amd/csrc/d3q19.h",
-                  "paper_1704_07559_amd/csrc/internal.h", "paper_1704_07559_amd/csrc/codec.h",
-                  "paper_1704_07559_amd/csrc/static_for.h", "paper_1704_07559_amd/csrc/reduce.h"]
+KERNEL_SOURCES = ["paper_1704_07559_amd/csrc/kernels_d3q19_step.hip", "paper_1704_07559_amd/csrc/d3q19_node.h",
+                  "paper_1704_07559_amd/csrc/d3q19.h", "paper_1704_07559_amd/csrc/internal.h",
+                  "paper_1704_07559_amd/csrc/codec.h", "paper_1704_07559_amd/csrc/static_for.h"]
 
 
 def log(msg):

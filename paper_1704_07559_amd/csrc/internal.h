@@ -218,8 +218,4 @@ struct StepIO {
 // strain-dependent viscosity, m^neq of rows 1, 9, 11, 13, 14, 15 and the strain's s_nu.
 inline int save_planes(const ViscF& V) { return V.kind == 0 ? 3 : 10; }
 
-// Reductions: 8 doubles per block, then one block sums the partials in a fixed order.
-constexpr int kReduceBlocks = 1024;
-constexpr int kReduceVals = 8;
-
 }  // namespace lbm

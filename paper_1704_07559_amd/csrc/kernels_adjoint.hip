@@ -286,76 +286,77 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ViscF V
                                                         const float* __restrict__ snu_f, float* __restrict__ lam_out,
                                                         float* __restrict__ grad_force, double* __restrict__ partials) {
   double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const unsigned stride = gridDim.x * blockDim.x;
-  for (unsigned idx = blockIdx.x * blockDim.x + threadIdx.x; idx < G.N; idx += stride) {
-    const int x = idx % G.nx;
-    const unsigned t = idx / G.nx;
-    const int y = t % G.ny;
-    const int z = t / G.ny;
-    const Nbr nb = neighbours(G, x, y, z);
-    const unsigned self = nb.self;
-    float g[Q];
-    pull<LatFwd, S>(buf, G, in_bytes<S>(nb), y, g);
-    const Pairs P = make_pairs(g);
-    const float drho = delta_rho(P);
-    float Fx, Fy, Fz;
-    force_at(Fo, G.N, self, Fx, Fy, Fz);
-    const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
-    const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
-    const float s1 = M.s[1], ir = M.inv_rho0;
-    float sn = M.s[9];
-    if (V.kind == 3) sn = implicit_rate_yu(n, M, V);
-    else if (V.kind != 0) sn = snu_f[self];
-    const float mn[6] = {n.m[1], n.m[9], n.m[11], n.m[13], n.m[14], n.m[15]};
-    const StrainParts sp = strain_parts(mn, s1, sn, ir);
-    const float* S6 = sp.S;
-    acc[0] += static_cast<double>(S6[0]) * S6[0] + static_cast<double>(S6[1]) * S6[1] +
-              static_cast<double>(S6[2]) * S6[2] +
-              2.0 * (static_cast<double>(S6[3]) * S6[3] + static_cast<double>(S6[4]) * S6[4] +
-                     static_cast<double>(S6[5]) * S6[5]);
-    // dJ/dS = 2 W S, and dJ/ds = (2 W S) . A at the strain's rate
-    float d6[6] = {2.0f * S6[0], 2.0f * S6[1], 2.0f * S6[2], 4.0f * S6[3], 4.0f * S6[4], 4.0f * S6[5]};
-    float dJds = 0.f;
+  // blocks take whole x-rows in turn; the threads of a block walk along the row
+  const unsigned rows = static_cast<unsigned>(G.ny) * G.nz;
+  for (unsigned r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int y = r % G.ny;
+    const int z = r / G.ny;
+    for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
+      const Nbr nb = neighbours(G, x, y, z);
+      const unsigned self = nb.self;
+      float g[Q];
+      pull<LatFwd, S>(buf, G, in_bytes<S>(nb), y, g);
+      const Pairs P = make_pairs(g);
+      const float drho = delta_rho(P);
+      float Fx, Fy, Fz;
+      force_at(Fo, G.N, self, Fx, Fy, Fz);
+      const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
+      const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
+      const float s1 = M.s[1], ir = M.inv_rho0;
+      float sn = M.s[9];
+      if (V.kind == 3) sn = implicit_rate_yu(n, M, V);
+      else if (V.kind != 0) sn = snu_f[self];
+      const float mn[6] = {n.m[1], n.m[9], n.m[11], n.m[13], n.m[14], n.m[15]};
+      const StrainParts sp = strain_parts(mn, s1, sn, ir);
+      const float* S6 = sp.S;
+      acc[0] += static_cast<double>(S6[0]) * S6[0] + static_cast<double>(S6[1]) * S6[1] +
+                static_cast<double>(S6[2]) * S6[2] +
+                2.0 * (static_cast<double>(S6[3]) * S6[3] + static_cast<double>(S6[4]) * S6[4] +
+                       static_cast<double>(S6[5]) * S6[5]);
+      // dJ/dS = 2 W S, and dJ/ds = (2 W S) . A at the strain's rate
+      float d6[6] = {2.0f * S6[0], 2.0f * S6[1], 2.0f * S6[2], 4.0f * S6[3], 4.0f * S6[4], 4.0f * S6[5]};
+      float dJds = 0.f;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) dJds += d6[c] * sp.A[c];
-    if (V.kind == 3) {
-      // the implicit rate moves with the state: ds/dm^neq = -k s (dgamma/dS)^T Y(s) / dG/ds
-      float dA = 0.f;
+      for (int c = 0; c < 6; ++c) dJds += d6[c] * sp.A[c];
+      if (V.kind == 3) {
+        // the implicit rate moves with the state: ds/dm^neq = -k s (dgamma/dS)^T Y(s) / dG/ds
+        float dA = 0.f;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) dA += sp.dg[c] * sp.A[c];
-      const float c0 = 3.0f * V.nu0 + 0.5f, k = 3.0f * V.csmag2;
-      const float cg = -dJds * sn * k / (c0 + k * sp.gamma + sn * k * dA);
+        for (int c = 0; c < 6; ++c) dA += sp.dg[c] * sp.A[c];
+        const float c0 = 3.0f * V.nu0 + 0.5f, k = 3.0f * V.csmag2;
+        const float cg = -dJds * sn * k / (c0 + k * sp.gamma + sn * k * dA);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) d6[c] = __builtin_fmaf(cg, sp.dg[c], d6[c]);
-    } else if (V.kind != 0) {
-      lam_out[19 * static_cast<size_t>(G.N) + self] = dJds;
-    }
-    // sigma = Y(s)^T dJ/dS on rows 1, 9, 11, 13..15 of m^neq
-    const YuT yv = yu_transpose(d6, s1, sn, ir);
-    float sg[Q];
+        for (int c = 0; c < 6; ++c) d6[c] = __builtin_fmaf(cg, sp.dg[c], d6[c]);
+      } else if (V.kind != 0) {
+        lam_out[19 * static_cast<size_t>(G.N) + self] = dJds;
+      }
+      // sigma = Y(s)^T dJ/dS on rows 1, 9, 11, 13..15 of m^neq
+      const YuT yv = yu_transpose(d6, s1, sn, ir);
+      float sg[Q];
 #pragma unroll
-    for (int k = 0; k < Q; ++k) sg[k] = 0.0f;
-    sg[1] = yv.r1;
-    sg[9] = yv.r9;
-    sg[11] = yv.r11;
-    sg[13] = yv.r13;
-    sg[14] = yv.r14;
-    sg[15] = yv.r15;
-    // lam = T^T sigma - (dm^eq/dg)^T sigma,  (dm^eq/dg)^T sigma = a 1 + C^T b
-    float lam[Q];
-    apply_transpose(sg, lam);
-    const float a = -11.0f * sg[1];
-    float bx, by, bz;
-    meq_j_transpose(yv, jx, jy, jz, ir, bx, by, bz);
-    static_for<Q>([&](auto ii) {
-      constexpr int i = ii;
-      lam[i] -= a + static_cast<float>(CX[i]) * bx + static_cast<float>(CY[i]) * by + static_cast<float>(CZ[i]) * bz;
-    });
-    store_local<Q>(lam_out, G, self * 4u, lam);
-    if (grad_force) {
-      grad_force[self] -= 0.5f * bx;
-      grad_force[G.N + self] -= 0.5f * by;
-      grad_force[2 * static_cast<size_t>(G.N) + self] -= 0.5f * bz;
+      for (int k = 0; k < Q; ++k) sg[k] = 0.0f;
+      sg[1] = yv.r1;
+      sg[9] = yv.r9;
+      sg[11] = yv.r11;
+      sg[13] = yv.r13;
+      sg[14] = yv.r14;
+      sg[15] = yv.r15;
+      // lam = T^T sigma - (dm^eq/dg)^T sigma,  (dm^eq/dg)^T sigma = a 1 + C^T b
+      float lam[Q];
+      apply_transpose(sg, lam);
+      const float a = -11.0f * sg[1];
+      float bx, by, bz;
+      meq_j_transpose(yv, jx, jy, jz, ir, bx, by, bz);
+      static_for<Q>([&](auto ii) {
+        constexpr int i = ii;
+        lam[i] -= a + static_cast<float>(CX[i]) * bx + static_cast<float>(CY[i]) * by + static_cast<float>(CZ[i]) * bz;
+      });
+      store_local<Q>(lam_out, G, self * 4u, lam);
+      if (grad_force) {
+        grad_force[self] -= 0.5f * bx;
+        grad_force[G.N + self] -= 0.5f * by;
+        grad_force[2 * static_cast<size_t>(G.N) + self] -= 0.5f * bz;
+      }
     }
   }
   block_reduce_store(acc, partials);
@@ -400,7 +401,7 @@ hipError_t launch_adjoint_step(const Geo& G, const ModelF& M, const ViscF& V, co
 hipError_t launch_loss_seed(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo,
                             const void* buf, const float* snu, float* lam_out, float* grad_force, double* partials,
                             double* out, hipStream_t st) {
-  unsigned nb = (G.N + 255) / 256;
+  unsigned nb = static_cast<unsigned>(G.ny) * G.nz;  // one x-row per block at a time
   if (nb > static_cast<unsigned>(kReduceBlocks)) nb = kReduceBlocks;
   switch (storage) {
     case 0: hipLaunchKernelGGL(loss_seed_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, static_cast<const float*>(buf), snu, lam_out, grad_force, partials); break;

@@ -204,38 +204,39 @@ template <typename S>
 __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
                                                      double* partials) {
   double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const unsigned stride = gridDim.x * blockDim.x;
-  for (unsigned idx = blockIdx.x * blockDim.x + threadIdx.x; idx < G.N; idx += stride) {
-    const int x = idx % G.nx;
-    const unsigned t = idx / G.nx;
-    const int y = t % G.ny;
-    const int z = t / G.ny;
-    const Nbr nb = neighbours(G, x, y, z);
-    float g[Q];
-    pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
-    int bad = 0;
+  // blocks take whole x-rows in turn; the threads of a block walk along the row
+  const unsigned rows = static_cast<unsigned>(G.ny) * G.nz;
+  for (unsigned r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int y = r % G.ny;
+    const int z = r / G.ny;
+    for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
+      const Nbr nb = neighbours(G, x, y, z);
+      float g[Q];
+      pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+      int bad = 0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);
-    const Pairs P = make_pairs(g);
-    const float drho = delta_rho(P);
-    float Fx, Fy, Fz;
-    load_force(Fo, G.N, nb.self, Fx, Fy, Fz);
-    const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
-    float S6[6];
-    strain_yu(noneq_moments(P, drho, jx, jy, jz, M.inv_rho0), M.s[1], snu_f ? snu_f[nb.self] : M.s[9], M.inv_rho0,
-              S6);
-    const double jj = static_cast<double>(jx) * jx + static_cast<double>(jy) * jy + static_cast<double>(jz) * jz;
-    acc[0] += drho;
-    acc[1] += jx;
-    acc[2] += jy;
-    acc[3] += jz;
-    acc[4] += jj * (0.5 / M.rho0);
-    acc[5] += static_cast<double>(S6[0]) * S6[0] + static_cast<double>(S6[1]) * S6[1] +
-              static_cast<double>(S6[2]) * S6[2] +
-              2.0 * (static_cast<double>(S6[3]) * S6[3] + static_cast<double>(S6[4]) * S6[4] +
-                     static_cast<double>(S6[5]) * S6[5]);
-    acc[6] = fmax(acc[6], sqrt(jj) / M.rho0);
-    acc[7] += bad;
+      for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);
+      const Pairs P = make_pairs(g);
+      const float drho = delta_rho(P);
+      float Fx, Fy, Fz;
+      load_force(Fo, G.N, nb.self, Fx, Fy, Fz);
+      const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
+      float S6[6];
+      strain_yu(noneq_moments(P, drho, jx, jy, jz, M.inv_rho0), M.s[1], snu_f ? snu_f[nb.self] : M.s[9], M.inv_rho0,
+                S6);
+      const double jj = static_cast<double>(jx) * jx + static_cast<double>(jy) * jy + static_cast<double>(jz) * jz;
+      acc[0] += drho;
+      acc[1] += jx;
+      acc[2] += jy;
+      acc[3] += jz;
+      acc[4] += jj * (0.5 / M.rho0);
+      acc[5] += static_cast<double>(S6[0]) * S6[0] + static_cast<double>(S6[1]) * S6[1] +
+                static_cast<double>(S6[2]) * S6[2] +
+                2.0 * (static_cast<double>(S6[3]) * S6[3] + static_cast<double>(S6[4]) * S6[4] +
+                       static_cast<double>(S6[5]) * S6[5]);
+      acc[6] = fmax(acc[6], sqrt(jj) / M.rho0);
+      acc[7] += bad;
+    }
   }
   block_reduce_store(acc, partials);
 }
@@ -319,7 +320,7 @@ hipError_t launch_set(int storage, const Geo& G, void* buf, const float* canon, 
 
 hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
                          const float* snu, double* partials, double* out, hipStream_t st) {
-  unsigned nb = (G.N + 255) / 256;
+  unsigned nb = static_cast<unsigned>(G.ny) * G.nz;  // one x-row per block at a time
   if (nb > static_cast<unsigned>(kReduceBlocks)) nb = kReduceBlocks;
   switch (storage) {
     case 0: hipLaunchKernelGGL(reduce_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, Fo, cb<float>(buf), snu, partials); break;

@@ -1,0 +1,171 @@
+// D3Q19 fused collide-stream-strain step.
+//
+// One thread owns one node. The step pulls the 19 post-collision populations of the
+// previous step from the neighbours (Eq. mrteq read backwards), forms the moments
+// m = T g (Section 2), the equilibrium moments (Eq. meq), the strain of this pre-collision
+// state by the Yu formula (Eq. LuoS) and/or the Chai formula (Eq. ChaiS), the new s_nu of
+// the viscosity model, relaxes in moment space (Eq. mrteqvT) and stores the 19
+// post-collision populations at the node itself. Loads are coalesced along x (shifted by
+// at most one element), stores are aligned and coalesced.
+#include <hip/hip_runtime.h>
+
+#include "d3q19.h"
+#include "d3q19_node.h"
+#include "internal.h"
+#include "launch.h"
+
+namespace lbm {
+namespace d3q19 {
+
+// Everything one node does between the pull and the store: moments, strain of the incoming
+// state (Yu and/or Chai, with the lagged s_nu or the implicitly solved one), viscosity
+// model, relaxation with the Guo term, back-transform. g holds the pulled pre-collision
+// populations on entry and the post-collision populations on exit; `self` is the node's
+// element offset in the fields.
+__device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const Geo& G, const ModelF& M,
+                                            const ViscF& V, const ForceF& Fo, const StepIO& io) {
+  const Pairs P_ = make_pairs(g);
+  const float drho = delta_rho(P_);
+  float jx = momentum<0>(P_), jy = momentum<1>(P_), jz = momentum<2>(P_);
+  float Fx, Fy, Fz;
+  load_force(Fo, G.N, self, Fx, Fy, Fz);
+  if (Fo.mode) {
+    jx = __builtin_fmaf(0.5f, Fx, jx);
+    jy = __builtin_fmaf(0.5f, Fy, jy);
+    jz = __builtin_fmaf(0.5f, Fz, jz);
+  }
+  const Neq n = noneq_moments(P_, drho, jx, jy, jz, M);
+
+  float Syu[6], Sch[6];
+  float snu = M.s[9];
+  float s_strain;  // the s_nu this step's strain is taken with
+  if (V.kind == 3) {
+    // implicit coupling: the strain at the rate of this very collision
+    snu = implicit_rate(P_, drho, jx, jy, jz, n, M, V);
+    s_strain = snu;
+    if (io.S_out) {
+      if (io.emit == 2) {
+        float r[Q];
+        rates_with(M, snu, r);
+        strain_chai(P_, drho, jx, jy, jz, r, M.inv_rho0, Sch);
+      } else {
+        strain_yu(n, M.s[1], snu, M.inv_rho0, Syu);
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
+    }
+  } else {
+    // lagged coupling: the strain of the incoming state with the rates of the previous collision
+    const float snu_prev = io.snu ? io.snu[self] : M.s[9];
+    s_strain = snu_prev;
+    const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
+    const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
+    if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
+    if (need_chai) {
+      float r[Q];
+      rates_with(M, snu_prev, r);
+      strain_chai(P_, drho, jx, jy, jz, r, M.inv_rho0, Sch);
+    }
+    if (io.S_out) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
+    }
+    // viscosity model -> s_nu of this collision (kept for the next step's strain)
+    if (V.kind != 0) {
+      snu = viscous_rate(V.drive_chai ? strain_sq(Sch) : strain_sq(Syu), V);
+      io.snu[self] = snu;
+    }
+  }
+
+  // Relaxation in moment space: dm_k = -s_k (m_k - m_k^eq) + (1 - s_k/2) S_F,k.
+  float dm[Q];
+  dm[0] = 0.0f;
+  dm[3] = Fx;
+  dm[5] = Fy;
+  dm[7] = Fz;
+  static_for<Q>([&](auto ki) {
+    constexpr int k = ki;
+    if constexpr (k != 0 && k != 3 && k != 5 && k != 7) {
+      const float sk = is_nu_slot(k) ? snu : M.s[k];
+      dm[k] = -sk * n.m[k];
+    }
+  });
+  if (Fo.mode) {
+    float SF[Q];
+    force_moments(jx, jy, jz, Fx, Fy, Fz, M.inv_rho0, SF);
+    static_for<Q>([&](auto ki) {
+      constexpr int k = ki;
+      if constexpr (k != 0 && k != 3 && k != 5 && k != 7 && k < 16) {
+        const float sk = is_nu_slot(k) ? snu : M.s[k];
+        dm[k] = __builtin_fmaf(1.0f - 0.5f * sk, SF[k], dm[k]);
+      }
+    });
+  }
+  add_back_transform(dm, g);
+
+  if (io.save) {
+    // what the adjoint of this step needs: j, and for a strain-dependent viscosity the
+    // non-equilibrium moments entering Eq. LuoS and the rate the strain was taken with
+    const size_t N = G.N;
+    stream_store(&io.save[self], jx);
+    stream_store(&io.save[N + self], jy);
+    stream_store(&io.save[2 * N + self], jz);
+    if (V.kind != 0) {
+      stream_store(&io.save[3 * N + self], n.m[1]);
+      stream_store(&io.save[4 * N + self], n.m[9]);
+      stream_store(&io.save[5 * N + self], n.m[11]);
+      stream_store(&io.save[6 * N + self], n.m[13]);
+      stream_store(&io.save[7 * N + self], n.m[14]);
+      stream_store(&io.save[8 * N + self], n.m[15]);
+      stream_store(&io.save[9 * N + self], s_strain);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// The fused step: one thread per node
+// ------------------------------------------------------------------------------------------
+template <typename S, bool WALLS, bool ROWS>
+__global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= G.nx || y >= G.ny) return;
+  const Nbr ne = neighbours(G, x, y, z);
+  const Nbr nb = in_bytes<S>(ne);
+  float g[Q];
+  pull<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, nb, y, g);
+  node_update(g, ne.self, G, M, V, Fo, io);
+  store_local<Q>(static_cast<S*>(io.dst), G, nb.self, g);
+}
+
+template <typename S>
+static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+                          const ForceF& Fo, const StepIO& io) {
+  // whole x-rows per block: every load may stream (see pull)
+  const bool rows = static_cast<int>(L.block.x) >= G.nx;
+  if (walls) {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, true, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  } else {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, false, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  }
+}
+
+hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,
+                       hipStream_t st) {
+  const Launch L = node_launch(G);
+  switch (storage) {
+    case 0: launch_step_t<float>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    case 1: launch_step_t<_Float16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    case 2: launch_step_t<__bf16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace d3q19
+}  // namespace lbm

@@ -1,11 +1,16 @@
 // Host-side launchers of the kernels (one translation unit per lattice), called by the C
-// ABI. Declarations only: nothing here changes the code of a kernel.
+// ABI, and the sizes of the reductions. Nothing here changes the code of the step kernels.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
 
 namespace lbm {
+
+// Reductions: 8 doubles per block (at most kReduceBlocks blocks, each taking whole x-rows),
+// then one block folds the partials in a fixed order.
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceVals = 8;
 
 namespace d3q19 {
 hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float* snu, const float* rho_u,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "launch.h"
 
 namespace lbm {
 
