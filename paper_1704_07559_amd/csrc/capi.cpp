@@ -68,6 +68,10 @@ lbm_status check_params(const lbm_params* p, int* Q, size_t* N) {
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 requires nz == 1");
   const size_t n = static_cast<size_t>(p->nx) * p->ny * p->nz;
   if (n >= (size_t(1) << 30)) return fail(LBM_EINVAL, "nx*ny*nz must be below 2^30 nodes");
+  // one z-plane of a population buffer (ny rows of Q runs of nx elements) is addressed with
+  // 32-bit byte offsets
+  if (static_cast<size_t>(p->nx) * p->ny * p->lattice * elem_size(p->storage) >= (size_t(1) << 32))
+    return fail(LBM_EINVAL, "nx*ny*Q*element size must be below 2^32 bytes");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be positive and finite");
   const int q = p->lattice;
   for (int k = 0; k < q; ++k)

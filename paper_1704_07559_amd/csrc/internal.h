@@ -36,8 +36,8 @@ struct ForceF {
 };
 
 // Node coordinates of the three source positions along each axis, indexed by c + 1:
-// the pull reads population i at x - c_i, so c = -1 -> x + 1, c = 0 -> x, c = +1 -> x - 1.
-// Offsets are in elements of one population plane; `self` is the node itself.
+// a pull reads element i at x - c_i, so c = -1 -> x + 1, c = 0 -> x, c = +1 -> x - 1.
+// Offsets are in elements of one plane of a node-indexed array; `self` is the node itself.
 struct Nbr {
   unsigned xs[3], ys[3], zs[3];
   unsigned self;
@@ -60,7 +60,7 @@ __device__ __forceinline__ Nbr neighbours(const Geo& G, int x, int y, int z) {
 }
 
 // The same offsets in bytes for elements of type S (N < 2^30 nodes keeps every byte offset
-// inside one population plane below 2^32).
+// inside one plane below 2^32).
 template <typename S>
 __device__ __forceinline__ Nbr in_bytes(const Nbr& n) {
   constexpr unsigned b = sizeof(S);
@@ -99,15 +99,10 @@ __device__ __forceinline__ bool crosses_wall(const Geo& G, int y) {
   else return G.walls && y == G.ny - 1;
 }
 
-// Pull streaming (the left side of Eq. mrteq): canonical g_i(x, n) = post-collision
-// population i of node x - c_i (periodic), or of population opp(i) at x across a wall.
-// nb holds byte offsets for S. With WALLS false the bounce test is compiled out and every
-// population plane is addressed from a wave-uniform base.
-// Cache policy: every population is read once per step, so loads are nontemporal, except
-// (ROW_BLOCKS false) the ten x-shifted populations when a block holds only part of an
-// x-row: their first or last cache line is also read by the neighbouring block, which
-// may run on another XCD, and a streaming hint there costs a refetch from HBM.
-template <class L, typename S, bool WALLS = true, bool ROW_BLOCKS = true>
+// Pull along -c on a node-indexed array (structure of arrays, plane i at i * N): element i
+// of node x - c_i (periodic), or element opp(i) of x across a y-wall. Used for the adjoint
+// state, whose transposed streaming is a pull along -c; nb holds byte offsets for S.
+template <class L, typename S, bool WALLS = true>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, const Nbr& nb, int y, float (&g)[L::Q]) {
   const char* cb = reinterpret_cast<const char*>(src);
   const size_t plane = static_cast<size_t>(G.N) * sizeof(S);
@@ -120,28 +115,119 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const Geo& G, co
         return;
       }
     }
-    if constexpr (L::cx(i) != 0 && !ROW_BLOCKS) g[i] = load_at_cached<S>(cb + i * plane, off);
-    else g[i] = load_at<S>(cb + i * plane, off);
+    g[i] = load_at<S>(cb + i * plane, off);
   });
 }
 
-// Inverse of pull: write canonical g_i(x) to the internal slot it is pulled from.
+// ---- internal population buffers -------------------------------------------------------
+// The two state buffers are row-interleaved: element (i, z, y, x) sits at
+// ((z * ny + y) * Q + i) * nx + x, so the Q populations of one x-row are Q consecutive runs
+// of nx elements. A wave's 2 Q streams then fall into the few DRAM pages of the 3 x 3 rows
+// around it instead of Q planes N elements apart. Addresses are a wave-uniform 64-bit base
+// (buffer + z-plane + population run) plus a 32-bit per-lane byte offset within the z-plane
+// (ny * Q * nx * sizeof(S) < 2^32, checked by lbm_init).
+template <int Q, typename S>
+struct Rows {
+  size_t zb[3];    // byte offsets of the z-planes z + 1, z, z - 1 (indexed by c + 1)
+  unsigned yb[3];  // byte offsets of the rows y + 1, y, y - 1 within a z-plane
+  unsigned xb[3];  // byte offsets of x + 1, x, x - 1 within a population run
+  unsigned self;   // yb[1] + xb[1]
+};
+
+template <int Q, typename S>
+__device__ __forceinline__ Rows<Q, S> rows_of(const Geo& G, int x, int y, int z) {
+  Rows<Q, S> r;
+  constexpr unsigned b = sizeof(S);
+  const unsigned row = static_cast<unsigned>(Q) * G.nx * b;
+  const size_t plane = static_cast<size_t>(G.ny) * row;
+  r.xb[0] = ((x == G.nx - 1) ? 0u : x + 1) * b;
+  r.xb[1] = x * b;
+  r.xb[2] = ((x == 0) ? G.nx - 1u : x - 1) * b;
+  r.yb[0] = ((y == G.ny - 1) ? 0u : y + 1) * row;
+  r.yb[1] = y * row;
+  r.yb[2] = ((y == 0) ? G.ny - 1u : y - 1) * row;
+  r.zb[0] = ((z == G.nz - 1) ? 0u : z + 1) * plane;
+  r.zb[1] = z * plane;
+  r.zb[2] = ((z == 0) ? G.nz - 1u : z - 1) * plane;
+  r.self = r.yb[1] + r.xb[1];
+  return r;
+}
+
+// Pull streaming (the left side of Eq. mrteq) from an internal buffer: canonical g_i(x, n)
+// is the post-collision population i of node x - c_i (periodic), or of population opp(i)
+// at x across a wall. With WALLS false the bounce test is compiled out.
+// Cache policy: every population is read once per step, so loads are nontemporal, except
+// (ROW_BLOCKS false) the x-shifted populations when a block holds only part of an x-row:
+// their first or last cache line is also read by the neighbouring block, which may run on
+// another XCD, and a streaming hint there costs a refetch from HBM.
+template <class L, typename S, bool WALLS = true, bool ROW_BLOCKS = true>
+__device__ __forceinline__ void pull_rows(const S* __restrict__ src, const Geo& G, const Rows<L::Q, S>& r, int y,
+                                          float (&g)[L::Q]) {
+  const char* cb = reinterpret_cast<const char*>(src);
+  const size_t run = static_cast<size_t>(G.nx) * sizeof(S);
+  static_for<L::Q>([&](auto ii) {
+    constexpr int i = ii;
+    if constexpr (WALLS && L::cy(i) != 0) {
+      if (crosses_wall<L::cy(i)>(G, y)) {
+        g[i] = load_at<S>(cb + r.zb[1] + L::opp(i) * run, r.self);
+        return;
+      }
+    }
+    const char* base = cb + r.zb[L::cz(i) + 1] + i * run;
+    const unsigned off = r.yb[L::cy(i) + 1] + r.xb[L::cx(i) + 1];
+    if constexpr (L::cx(i) != 0 && !ROW_BLOCKS) g[i] = load_at_cached<S>(base, off);
+    else g[i] = load_at<S>(base, off);
+  });
+}
+
+// Inverse of pull_rows: write canonical g_i(x) to the internal slot it is pulled from.
 template <class L, typename S>
-__device__ __forceinline__ void scatter(S* __restrict__ dst, const Geo& G, const Nbr& nb, int y,
-                                        const float (&g)[L::Q]) {
+__device__ __forceinline__ void scatter_rows(S* __restrict__ dst, const Geo& G, const Rows<L::Q, S>& r, int y,
+                                             const float (&g)[L::Q]) {
   char* cb = reinterpret_cast<char*>(dst);
-  const size_t plane = static_cast<size_t>(G.N) * sizeof(S);
+  const size_t run = static_cast<size_t>(G.nx) * sizeof(S);
   static_for<L::Q>([&](auto ii) {
     constexpr int i = ii;
     if (crosses_wall<L::cy(i)>(G, y)) {
-      store_at<S>(cb + L::opp(i) * plane, nb.self, g[i]);
+      store_at<S>(cb + r.zb[1] + L::opp(i) * run, r.self, g[i]);
     } else {
-      store_at<S>(cb + i * plane, nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[L::cx(i) + 1], g[i]);
+      store_at<S>(cb + r.zb[L::cz(i) + 1] + i * run, r.yb[L::cy(i) + 1] + r.xb[L::cx(i) + 1], g[i]);
     }
   });
 }
 
-// Store post-collision populations at the node itself (coalesced); byte offset of S.
+// Store post-collision populations at the node itself (aligned, coalesced).
+template <int Q, typename S>
+__device__ __forceinline__ void store_rows(S* __restrict__ dst, const Geo& G, const Rows<Q, S>& r,
+                                           const float (&g)[Q]) {
+  char* cb = reinterpret_cast<char*>(dst) + r.zb[1];
+  const size_t run = static_cast<size_t>(G.nx) * sizeof(S);
+  static_for<Q>([&](auto ii) {
+    constexpr int i = ii;
+    store_at<S>(cb + i * run, r.self, g[i]);
+  });
+}
+
+// Node index of (x, y, z) in the node-indexed fields (s_nu, forces, strain, canonical
+// populations, adjoint states): (z * ny + y) * nx + x.
+__device__ __forceinline__ unsigned node_index(const Geo& G, int x, int y, int z) {
+  return (static_cast<unsigned>(z) * G.ny + y) * G.nx + x;
+}
+
+// A node's index in the node-indexed fields together with its internal-buffer addresses.
+template <int Q, typename S>
+struct Node {
+  unsigned self;
+  Rows<Q, S> rows;
+};
+
+template <int Q, typename S>
+__device__ __forceinline__ Node<Q, S> node_at(const Geo& G, int x, int y, int z) {
+  return Node<Q, S>{node_index(G, x, y, z), rows_of<Q, S>(G, x, y, z)};
+}
+
+// Store Q values of node `self_bytes` (byte offset for S) into a node-indexed array
+// (structure of arrays, plane i at i * N): canonical populations and adjoint states.
 template <int Q, typename S>
 __device__ __forceinline__ void store_local(S* __restrict__ dst, const Geo& G, unsigned self_bytes,
                                             const float (&g)[Q]) {

@@ -292,10 +292,10 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ViscF V
     const int y = r % G.ny;
     const int z = r / G.ny;
     for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
-      const Nbr nb = neighbours(G, x, y, z);
+      const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
       const unsigned self = nb.self;
       float g[Q];
-      pull<LatFwd, S>(buf, G, in_bytes<S>(nb), y, g);
+      pull_rows<LatFwd, S>(buf, G, nb.rows, y, g);
       const Pairs P = make_pairs(g);
       const float drho = delta_rho(P);
       float Fx, Fy, Fz;

@@ -38,11 +38,10 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr ne = neighbours(G, x, y, 0);
-  const unsigned self = ne.self;
-  const Nbr nb = in_bytes<S>(ne);
+  const unsigned self = node_index(G, x, y, 0);
+  const Rows<Q, S> r = rows_of<Q, S>(G, x, y, 0);
   float g[Q];
-  pull<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, nb, y, g);
+  pull_rows<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, r, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P);
@@ -93,7 +92,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
     });
   }
   add_back_transform(dm, g);
-  store_local<Q>(static_cast<S*>(io.dst), G, nb.self, g);
+  store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
 template <typename S>
@@ -102,9 +101,9 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Forc
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, 0);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, 0);
   float g[Q];
-  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  pull_rows<Lat, S>(buf, G, nb.rows, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float Fx, Fy;
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, 0);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, 0);
   const unsigned self = nb.self;
   float drho = 0.f, ux = 0.f, uy = 0.f;
   if (rho_u) {
@@ -153,7 +152,7 @@ __global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf
     mn[8] = -(dxy + dyx) / (3.0f * sn);
     add_back_transform(mn, g);
   }
-  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  scatter_rows<Lat, S>(buf, G, nb.rows, y, g);
   if (snu) snu[self] = M.s[7];
 }
 
@@ -162,9 +161,9 @@ __global__ __launch_bounds__(kMaxBlock) void get_kernel(Geo G, const S* buf, flo
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, 0);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, 0);
   float g[Q];
-  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  pull_rows<Lat, S>(buf, G, nb.rows, y, g);
   store_local<Q>(canon, G, nb.self * 4u, g);
 }
 
@@ -173,11 +172,11 @@ __global__ __launch_bounds__(kMaxBlock) void set_kernel(Geo G, S* buf, const flo
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, 0);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, 0);
   float g[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = canon[static_cast<size_t>(i) * G.N + nb.self];
-  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  scatter_rows<Lat, S>(buf, G, nb.rows, y, g);
 }
 
 template <typename S>
@@ -187,9 +186,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo,
   // blocks take whole x-rows in turn; the threads of a block walk along the row
   for (int y = blockIdx.x; y < G.ny; y += gridDim.x) {
     for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
-      const Nbr nb = neighbours(G, x, y, 0);
+      const Node<Q, S> nb = node_at<Q, S>(G, x, y, 0);
       float g[Q];
-      pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+      pull_rows<Lat, S>(buf, G, nb.rows, y, g);
       int bad = 0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);

@@ -44,11 +44,10 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr ne = neighbours(G, x, y, z);
-  const unsigned self = ne.self;
-  const Nbr nb = in_bytes<S>(ne);
+  const unsigned self = node_index(G, x, y, z);
+  const Rows<Q, S> r = rows_of<Q, S>(G, x, y, z);
   float g[Q];
-  pull<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, nb, y, g);
+  pull_rows<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, r, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P), jz = momentum<2>(P);
@@ -103,7 +102,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
     });
   }
   add_back_transform(dm, g);
-  store_local<Q>(static_cast<S*>(io.dst), G, nb.self, g);
+  store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
 template <typename S>
@@ -113,9 +112,9 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Forc
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   float g[Q];
-  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  pull_rows<Lat, S>(buf, G, nb.rows, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float Fx, Fy, Fz;
@@ -141,7 +140,7 @@ __global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   const unsigned self = nb.self;
   const size_t N = G.N;
   float drho = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
@@ -171,7 +170,7 @@ __global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf
     mn[13] = -(d[2] + d[6]) / (3.0f * sn);
     add_back_transform(mn, g);
   }
-  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  scatter_rows<Lat, S>(buf, G, nb.rows, y, g);
   if (snu) snu[self] = M.s[9];
 }
 
@@ -181,9 +180,9 @@ __global__ __launch_bounds__(kMaxBlock) void get_kernel(Geo G, const S* buf, flo
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   float g[Q];
-  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  pull_rows<Lat, S>(buf, G, nb.rows, y, g);
   store_local<Q>(canon, G, nb.self * 4u, g);
 }
 
@@ -193,11 +192,11 @@ __global__ __launch_bounds__(kMaxBlock) void set_kernel(Geo G, S* buf, const flo
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   float g[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = canon[static_cast<size_t>(i) * G.N + nb.self];
-  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  scatter_rows<Lat, S>(buf, G, nb.rows, y, g);
 }
 
 template <typename S>
@@ -210,9 +209,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo,
     const int y = r % G.ny;
     const int z = r / G.ny;
     for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
-      const Nbr nb = neighbours(G, x, y, z);
+      const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
       float g[Q];
-      pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+      pull_rows<Lat, S>(buf, G, nb.rows, y, g);
       int bad = 0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);

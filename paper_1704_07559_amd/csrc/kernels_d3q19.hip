@@ -22,9 +22,9 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Visc
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   float g[Q];
-  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  pull_rows<Lat, S>(buf, G, nb.rows, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P), jz = momentum<2>(P);
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   const unsigned self = nb.self;
   float drho = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
   if (rho_u) {
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kMaxBlock) void init_kernel(Geo G, ModelF M, S* buf
     mn[15] = -(d[2] + d[6]) / (3.0f * sn);
     add_neq_from_moments(mn, g);
   }
-  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  scatter_rows<Lat, S>(buf, G, nb.rows, y, g);
   if (snu) snu[self] = M.s[9];
 }
 
@@ -97,9 +97,9 @@ __global__ __launch_bounds__(kMaxBlock) void get_kernel(Geo G, const S* buf, flo
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   float g[Q];
-  pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  pull_rows<Lat, S>(buf, G, nb.rows, y, g);
   store_local<Q>(canon, G, nb.self * 4u, g);
 }
 
@@ -109,11 +109,11 @@ __global__ __launch_bounds__(kMaxBlock) void set_kernel(Geo G, S* buf, const flo
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr nb = neighbours(G, x, y, z);
+  const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
   float g[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = canon[static_cast<size_t>(i) * G.N + nb.self];
-  scatter<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+  scatter_rows<Lat, S>(buf, G, nb.rows, y, g);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -129,9 +129,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ViscF V, F
     const int y = r % G.ny;
     const int z = r / G.ny;
     for (int x = threadIdx.x; x < G.nx; x += blockDim.x) {
-      const Nbr nb = neighbours(G, x, y, z);
+      const Node<Q, S> nb = node_at<Q, S>(G, x, y, z);
       float g[Q];
-      pull<Lat, S>(buf, G, in_bytes<S>(nb), y, g);
+      pull_rows<Lat, S>(buf, G, nb.rows, y, g);
       int bad = 0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) bad += !isfinite(g[i]);

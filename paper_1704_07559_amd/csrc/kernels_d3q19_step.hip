@@ -133,12 +133,11 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
-  const Nbr ne = neighbours(G, x, y, z);
-  const Nbr nb = in_bytes<S>(ne);
+  const Rows<Q, S> r = rows_of<Q, S>(G, x, y, z);
   float g[Q];
-  pull<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, nb, y, g);
-  node_update(g, ne.self, G, M, V, Fo, io);
-  store_local<Q>(static_cast<S*>(io.dst), G, nb.self, g);
+  pull_rows<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, r, y, g);
+  node_update(g, node_index(G, x, y, z), G, M, V, Fo, io);
+  store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
 template <typename S>

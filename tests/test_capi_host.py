@@ -52,6 +52,10 @@ def test_size_limits_and_other_lattices():
     assert capi.lbm_population_bytes(capi.Params(nx=1024, ny=1024, nz=1023, s=s)) == 19 * 4 * 1024 * 1024 * 1023
     assert capi.lbm_population_bytes(capi.Params(nx=1024, ny=1024, nz=1024, s=s)) == 0
     assert capi.lbm_population_bytes(capi.Params(nx=1, ny=1, nz=1, s=s)) == 19 * 4
+    # one z-plane of the row-interleaved buffer (ny * 19 * nx elements) must stay below 4 GiB
+    assert capi.lbm_population_bytes(capi.Params(nx=8192, ny=8192, nz=1, s=s)) == 0
+    assert capi.lbm_population_bytes(capi.Params(nx=8192, ny=8192, nz=1, s=s, storage=capi.LBM_F16)) == \
+        19 * 2 * 8192 * 8192
     s15 = [0.0, 1.6, 1.2, 0.0, 1.6, 0.0, 1.6, 0.0, 1.6, 1.25, 1.25, 1.25, 1.25, 1.25, 1.2] + [0.0] * 4
     assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=capi.LBM_D3Q15, s=s15)) == 15 * 4 * 120
     uneq = list(s15)
