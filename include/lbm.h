@@ -18,16 +18,18 @@
  *   - Populations are the deviations g_i = f_i - w_i rho0 (the delta-rho form of Eq. edf),
  *     i in the velocity order of Eq. HeLuoD3Q19 (D3Q19), (0, E, N, W, S, NE, NW, SW, SE)
  *     (D2Q9), or (0, +x, -x, +y, -y, +z, -z, (+++), (---), (++-), (--+), (+-+), (-+-),
- *     (-++), (+--)) (D3Q15). "Canonical" populations are the pre-collision g_i(x, n) of Eq. mrteq. The
- *     library keeps its own internal layout in the two state buffers; only
- *     lbm_get_populations / lbm_set_populations / lbm_init convert.
+ *     (-++), (+--)) (D3Q15). "Canonical" populations are the pre-collision g_i(x, n) of
+ *     Eq. mrteq, as a Q-component field. The two state buffers use the library's own
+ *     layout (row-interleaved post-collision populations, element (i, z, y, x) at
+ *     ((z*ny + y)*Q + i)*nx + x); only lbm_get_populations / lbm_set_populations /
+ *     lbm_init convert, and lbm_save_state / lbm_load_state copy it as it is.
  *   - Strain fields hold 6 components (xx, yy, zz, xy, yz, xz) for D3Q19 and D3Q15 and 3
  *     components (xx, yy, xy) for D2Q9, of the strain of the pre-collision state.
  *   - Lattice units: delta_x = delta_t = 1, c_s^2 = 1/3.
  *   - Every pointer argument named as a field is a DEVICE pointer, caller-owned, and must
- *     stay valid while the context uses it. Buffers must be 256-byte aligned. No entry
- *     point allocates device memory except lbm_init (a small reduction scratch) and none
- *     frees caller memory.
+ *     stay valid while the context uses it. Population buffers must be 256-byte aligned,
+ *     other fields 4-byte aligned. No entry point allocates device memory except lbm_init
+ *     (a small reduction scratch) and none frees caller memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call is
  *     asynchronous on that stream, except where a host result is returned (lbm_reduce,
  *     lbm_strain_loss_seed), which synchronise the stream before returning.
