@@ -169,3 +169,81 @@ def test_gpu_gradient_against_gpu_finite_differences():
     ad_F = float((F_t.grad.double() * dF.double()).sum())
     assert abs(fd_u - ad_u) < 1e-3 * abs(ad_u), (fd_u, ad_u)
     assert abs(fd_F - ad_F) < 1e-3 * abs(ad_F), (fd_F, ad_F)
+
+
+@pytest.mark.slow
+def test_adjoint_step_128_cubed_sampled_against_oracle():
+    """The adjoint kernel at the benchmarked size (128^3, force field, constant viscosity),
+    in that launch configuration: one reverse step from a random far-from-equilibrium
+    state and a random adjoint state, checked at sampled nodes against the FP64 oracle
+    evaluated on each node's 3 x 3 x 3 neighbourhood (the step at a node reads no other
+    node)."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    from tests._common import sample_nodes
+    n = 128
+    shape = (n, n, n)
+    F = synth.uniform_random_force(shape, seed=7559, amp=1e-6).astype(np.float32).astype(np.float64)
+    op, cp, _ = spec_params(shape, tau=0.8, force=F)
+    g = _state(shape, 21, op)
+    sim = lbm.LBM(cp)
+    sim.set_populations(torch.as_tensor(g.astype(np.float32)).cuda())
+    N = cp.N
+    rec = torch.empty((1, 3, N), device="cuda")
+    sim.step(1, save=rec)
+    lam = synth.random_state(19, shape, seed=22, scale=1.0).astype(np.float32).astype(np.float64)
+    lam_t = torch.as_tensor(lam.astype(np.float32)).cuda().reshape(19, N)
+    out = torch.empty_like(lam_t)
+    gF = torch.zeros((3, N), device="cuda")
+    capi.lbm_adjoint_step(sim.ctx, rec[0], lam_t, out, gF)
+    out = out.reshape((19,) + shape)
+    gF = gF.reshape((3,) + shape)
+    worst, worst_F = 0.0, 0.0
+    scale, scale_F = 0.0, 0.0
+    for (z, y, x) in sample_nodes(shape, 30, 23):
+        ix = np.ix_([(z + d) % n for d in (-1, 0, 1)], [(y + d) % n for d in (-1, 0, 1)],
+                    [(x + d) % n for d in (-1, 0, 1)])
+        gp = np.stack([g[i][ix] for i in range(19)])
+        lp = np.stack([lam[i][ix] for i in range(19)])
+        Fp = np.stack([F[c][ix] for c in range(3)])
+        ref_l, ref_F = adj.adjoint_step(lp, gp, Fp, adj._with_force(op, Fp))
+        got = out[:, z, y, x].double().cpu().numpy()
+        got_F = gF[:, z, y, x].double().cpu().numpy()
+        worst = max(worst, float(np.abs(got - ref_l[:, 1, 1, 1]).max()))
+        worst_F = max(worst_F, float(np.abs(got_F - ref_F[:, 1, 1, 1]).max()))
+        scale = max(scale, float(np.abs(ref_l[:, 1, 1, 1]).max()))
+        scale_F = max(scale_F, float(np.abs(ref_F[:, 1, 1, 1]).max()))
+    assert worst < 1e-5 * scale and worst_F < 1e-5 * scale_F, (worst / scale, worst_F / scale_F)
+    sim.close()
+
+
+@pytest.mark.slow
+def test_gradient_128_cubed_500_steps_against_gpu_finite_differences():
+    """The whole benchmarked gradient (128^3, 500 steps, checkpoint every 50): directional
+    derivatives of J by five-point central differences of the GPU forward, a property that
+    holds at any size, against the adjoint gradient."""
+    import torch
+    from paper_1704_07559_amd import autograd as ag
+    shape, u0, F = _c4(128)
+    op, cp, _ = spec_params(shape, tau=0.8)
+    prob = ag.StrainLossProblem(cp, 500, 50)
+    u0_t = torch.as_tensor(u0.astype(np.float32)).cuda().requires_grad_(True)
+    F_t = torch.as_tensor(F.astype(np.float32)).cuda().requires_grad_(True)
+    ag.strain_loss(u0_t, F_t, prob).backward()
+    du = torch.as_tensor(synth.random_vector(shape, seed=5, scale=1.0).astype(np.float32)).cuda()
+    dF = torch.as_tensor(synth.random_vector(shape, seed=6, scale=1.0).astype(np.float32)).cuda()
+
+    def J(u, f):
+        with torch.no_grad():
+            return ag.strain_loss(u, f, prob).item()
+
+    def fd5(fun, h):
+        return (8 * (fun(h) - fun(-h)) - (fun(2 * h) - fun(-2 * h))) / (12 * h)
+
+    u_d, F_d = u0_t.detach(), F_t.detach()
+    fd_u = fd5(lambda t: J(u_d + t * du, F_d), 1e-3 * float(u_d.abs().max()))
+    fd_F = fd5(lambda t: J(u_d, F_d + t * dF), 1e-5)
+    ad_u = float((u0_t.grad.double() * du.double()).sum())
+    ad_F = float((F_t.grad.double() * dF.double()).sum())
+    assert abs(fd_u - ad_u) < 2e-3 * abs(ad_u), (fd_u, ad_u)
+    assert abs(fd_F - ad_F) < 2e-3 * abs(ad_F), (fd_F, ad_F)

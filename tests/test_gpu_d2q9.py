@@ -106,3 +106,39 @@ def test_taylor_green_64_squared_800_steps():
     assert np.linalg.norm(S - exact) / np.linalg.norm(exact) < 2e-3
     d = sim.reduce()
     assert d["nonfinite"] == 0 and abs(d["mass"] - dr.sum()) < 1e-4 * np.abs(dr).sum()
+
+
+@pytest.mark.slow
+def test_les_4096_squared_sampled():
+    """The D2Q9 workload bench.py times (4096^2, FP32, Smagorinsky C_s = 0.1 from the Yu-type
+    strain, tau_nu0 = 0.51), in that launch configuration: two steps, then populations and
+    the strain of both steps at sampled nodes against the FP64 oracle run on each node's
+    5 x 5 neighbourhood (a node after k steps depends only on its radius-k neighbourhood)."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    from tests._common import sample_nodes
+    m, K = 4096, 2
+    shape = (1, m, m)
+    u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)[:2]
+    kw = dict(visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    op, cp = _spec(shape, tau=0.51, **kw)
+    sim = lbm.LBM(cp, lbm.rho_u_field(np.zeros(shape), u))
+    S = [torch.empty((3,) + shape, device="cuda") for _ in range(K)]
+    for k in range(K):
+        sim.step(1, S_out=S[k], strain_kind=capi.LBM_STRAIN_YU)
+    g = sim.populations()
+    d = sim.reduce()
+    worst_g, dS, fr = 0.0, 0.0, 0.0
+    for (_, y, x) in sample_nodes(shape, 30, 9):
+        ix = np.ix_([0], [(y + t) % m for t in range(-K, K + 1)], [(x + t) % m for t in range(-K, K + 1)])
+        up = np.stack([u[c][ix] for c in range(2)])
+        ref = od.Simulation(op, od.init_populations(np.zeros(up.shape[1:]), up, op))
+        S_ref = [ref.step(1)[0][:, 0, K, K] for _ in range(K)]
+        got = g[:, 0, y, x].double().cpu().numpy()
+        worst_g = max(worst_g, _pop_err(got[:, None, None, None], ref.g[:, :, K:K + 1, K:K + 1]))
+        for k in range(K):
+            dS = max(dS, float(np.abs(S[k][:, 0, y, x].double().cpu().numpy() - S_ref[k]).max()))
+            fr = max(fr, float(np.sqrt(S_ref[k][0] ** 2 + S_ref[k][1] ** 2 + 2 * S_ref[k][2] ** 2)))
+    sim.close()
+    assert worst_g < 1e-5 and dS / fr < 1e-4, (worst_g, dS / fr)
+    assert d["nonfinite"] == 0
