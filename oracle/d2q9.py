@@ -162,6 +162,22 @@ def viscosity_rate(S, p: Params, s_nu_const: float):
     return 1.0 / (3.0 * nu + 0.5)
 
 
+def implicit_smagorinsky_rate(S_of_s, p: Params, shape):
+    """s_nu solving s = 1 / (3 (nu0 + C_s^2 |S(s)|) + 1/2) per node, S(s) being the strain
+    formula at s_nu = s. The Yu-type formula is affine in s_nu with an isotropic s_e part and a
+    traceless s_nu part, so |S(s)| increases with s and the root in (0, 2] is unique: plain
+    bisection to FP64 resolution."""
+    lo = np.zeros(shape)
+    hi = np.full(shape, 2.0)
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        nu = p.nu0 + p.c_smag**2 * np.sqrt(2.0 * strain_sq(S_of_s(mid)))
+        f = mid * (3.0 * nu + 0.5) - 1.0
+        lo = np.where(f < 0.0, mid, lo)
+        hi = np.where(f < 0.0, hi, mid)
+    return 0.5 * (lo + hi)
+
+
 def rates_field(p: Params, s_nu):
     s = np.broadcast_to(p.s.reshape((Q,) + (1,) * s_nu.ndim), (Q,) + s_nu.shape).copy()
     for k in NU_SLOTS:
@@ -176,10 +192,22 @@ def collide(g, p: Params, s_nu_prev):
     drho, j = macroscopic(g, F)
     m = np.tensordot(T, g, axes=(1, 0))
     meq = m_eq(drho, j, p.rho0)
-    sp = rates_field(p, s_nu_prev)
-    S_yu = strain_yu_type(m - meq, sp, p.rho0)
-    S_chai = strain_chai(g - g_eq(drho, j, p.rho0), sp, p.rho0)
-    s_nu = viscosity_rate(S_yu if p.visc_strain == "yu" else S_chai, p, float(p.s[7]))
+    f_neq = g - g_eq(drho, j, p.rho0)
+    if p.visc_kind == "smagorinsky_implicit":
+        # non-lagged coupling: the strain uses the rate of this very collision
+        def yu_of(sv):
+            return strain_yu_type(m - meq, rates_field(p, sv), p.rho0)
+
+        def chai_of(sv):
+            return strain_chai(f_neq, rates_field(p, sv), p.rho0)
+
+        s_nu = implicit_smagorinsky_rate(yu_of if p.visc_strain == "yu" else chai_of, p, g.shape[1:])
+        S_yu, S_chai = yu_of(s_nu), chai_of(s_nu)
+    else:
+        sp = rates_field(p, s_nu_prev)
+        S_yu = strain_yu_type(m - meq, sp, p.rho0)
+        S_chai = strain_chai(f_neq, sp, p.rho0)
+        s_nu = viscosity_rate(S_yu if p.visc_strain == "yu" else S_chai, p, float(p.s[7]))
     s = rates_field(p, s_nu)
     SF = np.tensordot(T, guo_force_populations(j, F, p.rho0), axes=(1, 0))
     m_post = m - s * (m - meq) + (1.0 - 0.5 * s) * SF
@@ -204,6 +232,9 @@ def stream(g_post, walls_y=False):
 
 
 def strain_of_state(g, p: Params, s_nu, kind="yu"):
+    if p.visc_kind == "smagorinsky_implicit":
+        _, S_yu, S_chai, _ = collide(g, p, s_nu)
+        return S_yu if kind == "yu" else S_chai
     F = p.force_field(g.shape[1:])
     drho, j = macroscopic(g, F)
     s = rates_field(p, s_nu)

@@ -135,3 +135,34 @@ def test_second_order_convergence_of_S_xy_d2q9():
         errs.append(np.linalg.norm(sim.strain("yu")[2] - exact) / np.linalg.norm(exact))
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert (orders >= 1.8).all(), (errs, orders)
+
+
+def test_implicit_smagorinsky_rate_is_a_fixed_point():
+    """The non-lagged coupling: the solved s_nu satisfies s = 1/(3 (nu0 + C^2 |S(s)|) + 1/2)
+    to FP64 resolution for either driving formula, both formulas agree at the solved rate,
+    and C_s = 0 recovers the molecular rate."""
+    shape = (1, 5, 7)
+    g = synth.random_state(9, shape, seed=41, scale=0.02)
+    for drive in ("yu", "chai"):
+        p = d.Params(visc_kind="smagorinsky_implicit", visc_strain=drive, nu0=0.002, c_smag=0.3)
+        _, S_yu, S_chai, s_nu = d.collide(g, p, np.full(shape, p.s[7]))
+        S = S_yu if drive == "yu" else S_chai
+        lhs = s_nu * (3.0 * (p.nu0 + p.c_smag**2 * np.sqrt(2.0 * d.strain_sq(S))) + 0.5)
+        assert np.abs(lhs - 1.0).max() < 1e-14
+        assert np.abs(S_yu - S_chai).max() <= 1e-13 * np.abs(S_yu).max()
+        assert np.abs(d.strain_of_state(g, p, np.full(shape, p.s[7]), drive) - S).max() == 0.0
+        p0 = d.Params(visc_kind="smagorinsky_implicit", visc_strain=drive, nu0=0.1, c_smag=0.0)
+        assert np.abs(d.collide(g, p0, np.full(shape, p.s[7]))[3] - 1.0 / 0.8).max() < 1e-14
+
+
+def test_implicit_smagorinsky_conserves():
+    shape = (1, 5, 7)
+    p = d.Params(visc_kind="smagorinsky_implicit", nu0=0.01, c_smag=0.2)
+    u = synth.random_vector(shape, seed=42, scale=0.03)[:2]
+    sim = d.Simulation(p, d.init_populations(np.zeros(shape), u, p))
+    m0 = sim.g.sum()
+    j0 = np.tensordot(d.C.astype(float), sim.g, axes=(1, 0)).reshape(2, -1).sum(1)
+    sim.step(20)
+    assert abs(sim.g.sum() - m0) < 1e-13
+    j1 = np.tensordot(d.C.astype(float), sim.g, axes=(1, 0)).reshape(2, -1).sum(1)
+    assert np.abs(j1 - j0).max() < 1e-13
