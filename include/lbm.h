@@ -83,9 +83,10 @@ typedef enum {
  *             nu = nu_max (n_pl < 1) or nu_min (n_pl > 1) at |S| = 0. |S| = sqrt(2 S:S).
  *             s_nu = 1/(3 nu + 1/2) relaxes the collision; the strain of the next step
  *             uses the s_nu of the previous collision at the node (held in s_nu_field).
- *             LBM_VISC_SMAGORINSKY_IMPLICIT (D3Q19 only): no lagged field; every node solves
- *             s_nu = 1/(3 (nu0 + c_smag^2 |S(s_nu)|) + 1/2), S(s_nu) being the strain formula
- *             (affine in s_nu) at the rate of this very collision; s_nu_field may be NULL.
+ *             LBM_VISC_SMAGORINSKY_IMPLICIT (every lattice): no lagged field; every node
+ *             solves s_nu = 1/(3 (nu0 + c_smag^2 |S(s_nu)|) + 1/2), S(s_nu) being the strain
+ *             formula (affine in s_nu) at the rate of this very collision; s_nu_field may be
+ *             NULL.
  *  visc_strain which formula drives the viscosity (LBM_STRAIN_YU or LBM_STRAIN_CHAI).
  *  walls_y    0: periodic in y. 1: halfway bounce-back walls at y = -1/2 and y = ny - 1/2.
  *  force[3]   uniform body force (Guo forcing, j = sum c g + F/2) used when

@@ -91,8 +91,6 @@ lbm_status check_params(const lbm_params* p, int* Q, size_t* N) {
   if (!(p->s[snu_slot] > 0.0)) return fail(LBM_EINVAL, "s_nu must be positive");
   if (p->visc_kind < LBM_VISC_CONST || p->visc_kind > LBM_VISC_SMAGORINSKY_IMPLICIT)
     return fail(LBM_EINVAL, "bad visc_kind");
-  if (p->visc_kind == LBM_VISC_SMAGORINSKY_IMPLICIT && q != 19)
-    return fail(LBM_EUNSUPPORTED, "the implicit Smagorinsky coupling is provided for D3Q19");
   if (p->visc_kind != LBM_VISC_CONST && p->visc_strain != LBM_STRAIN_YU && p->visc_strain != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "visc_strain must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
   if ((p->visc_kind == LBM_VISC_SMAGORINSKY || p->visc_kind == LBM_VISC_SMAGORINSKY_IMPLICIT) && !(p->nu0 >= 0.0))
@@ -270,8 +268,8 @@ lbm_status lbm_strain(lbm_ctx* c, int strain_kind, float* S_out, void* stream) {
   hipError_t e;
   switch (c->Q) {
     case 19: e = d3q19::launch_strain(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
-    case 15: e = d3q15::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
-    default: e = d2q9::launch_strain(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
+    case 15: e = d3q15::launch_strain(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
+    default: e = d2q9::launch_strain(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, strain_kind, S_out, s); break;
   }
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_strain");
 }
@@ -286,8 +284,8 @@ lbm_status lbm_reduce(lbm_ctx* c, double* host_out, void* stream) {
   hipError_t e;
   switch (c->Q) {
     case 19: e = d3q19::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
-    case 15: e = d3q15::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
-    default: e = d2q9::launch_reduce(c->p.storage, c->G, c->M, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
+    case 15: e = d3q15::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
+    default: e = d2q9::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
   }
   if (e != hipSuccess) return hip_fail(e, "lbm_reduce");
   e = hipMemcpyAsync(host_out, dout, sizeof(double) * kReduceVals, hipMemcpyDeviceToHost, s);

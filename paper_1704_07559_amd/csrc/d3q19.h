@@ -272,34 +272,6 @@ __device__ __forceinline__ void strain_chai(const Pairs& P, float drho, float jx
   });
 }
 
-// Implicit Smagorinsky coupling: both strain formulas are affine in s_nu, S(s) = P + s A
-// (P from the s_e and s_c rows, A from the s_nu rows). Returns the s > 0 solving
-//   s (c + k |P + s A|) = 1,  c = 3 nu0 + 1/2, k = 3 C_s^2, |S| = sqrt(2 S:S),
-// whose left side increases with s. Newton from the root of the P = 0 case,
-// k sqrt(2 A:A) s^2 + c s - 1 = 0; three steps reach FP32 resolution.
-__device__ __forceinline__ float implicit_smagorinsky(const float (&P)[6], const float (&A)[6], float nu0,
-                                                     float csmag2) {
-  const float c = 3.0f * nu0 + 0.5f, k = 3.0f * csmag2;
-  float PP = 0.f, PA = 0.f, AA = 0.f;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const float w = i < 3 ? 1.0f : 2.0f;
-    PP += w * P[i] * P[i];
-    PA += w * P[i] * A[i];
-    AA += w * A[i] * A[i];
-  }
-  const float q = k * sqrtf(2.0f * AA);
-  float s = 2.0f / (c + sqrtf(c * c + 4.0f * q));
-#pragma unroll
-  for (int it = 0; it < 3; ++it) {
-    const float r = sqrtf(fmaxf(2.0f * (PP + s * (2.0f * PA + s * AA)), 0.0f));
-    const float dr = r > 0.0f ? 2.0f * (PA + s * AA) / r : 0.0f;
-    const float f = s * (c + k * r) - 1.0f;
-    s -= f / (c + k * r + s * k * dr);
-  }
-  return s;
-}
-
 // The implicit Smagorinsky rate at one node from the Yu strain of the non-equilibrium
 // moments (the Chai strain is the same function of the state, Section 5.1).
 __device__ __forceinline__ float implicit_rate_yu(const Neq& n, const ModelF& M, const ViscF& V) {

@@ -261,6 +261,39 @@ __device__ __forceinline__ float viscous_slope(float gamma, const ViscF& V) {
   return (nu > V.numin && nu < V.numax) ? (V.npl - 1.0f) * nu / gamma : 0.0f;
 }
 
+// Implicit Smagorinsky coupling. Every strain formula here (Yu, Chai, and the Yu-type
+// formulas of the other lattices) is affine in s_nu: S(s) = P + s A, P from the rows relaxed
+// at the other rates, A from the s_nu rows. Returns the s > 0 solving
+//   s (c + k |P + s A|) = 1,  c = 3 nu0 + 1/2, k = 3 C_s^2, |S| = sqrt(2 S:S),
+// whose left side increases with s. NC = 6 (3D, xx yy zz xy xz yz) or 3 (2D, xx yy xy);
+// off-diagonal components count twice in S:S. Newton from the root of the P = 0 case,
+// k sqrt(2 A:A) s^2 + c s - 1 = 0; three steps reach FP32 resolution.
+template <int NC>
+__device__ __forceinline__ float implicit_smagorinsky(const float (&P)[NC], const float (&A)[NC], float nu0,
+                                                     float csmag2) {
+  static_assert(NC == 6 || NC == 3, "3D or 2D symmetric tensor");
+  constexpr int ndiag = NC == 6 ? 3 : 2;
+  const float c = 3.0f * nu0 + 0.5f, k = 3.0f * csmag2;
+  float PP = 0.f, PA = 0.f, AA = 0.f;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    const float w = i < ndiag ? 1.0f : 2.0f;
+    PP += w * P[i] * P[i];
+    PA += w * P[i] * A[i];
+    AA += w * A[i] * A[i];
+  }
+  const float q = k * sqrtf(2.0f * AA);
+  float s = 2.0f / (c + sqrtf(c * c + 4.0f * q));
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    const float r = sqrtf(fmaxf(2.0f * (PP + s * (2.0f * PA + s * AA)), 0.0f));
+    const float dr = r > 0.0f ? 2.0f * (PA + s * AA) / r : 0.0f;
+    const float f = s * (c + k * r) - 1.0f;
+    s -= f / (c + k * r + s * k * dr);
+  }
+  return s;
+}
+
 // Launch shape for the node-parallel kernels: one thread per node, blocks of (TX, TY)
 // nodes (at most kMaxBlock threads), grid (ceil(nx/TX), ceil(ny/TY), nz).
 constexpr int kMaxBlock = 256;

@@ -38,6 +38,35 @@ __device__ __forceinline__ float strain_sq(const float (&S)[6]) {
   return S[0] * S[0] + S[1] * S[1] + S[2] * S[2] + 2.0f * (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
 }
 
+// s_nu of the implicit Smagorinsky coupling at one node, from the formula V selects (both
+// are affine in s_nu: split into the part at the other rates and the s_nu rows).
+__device__ __forceinline__ float implicit_rate(const Pairs& P_, float drho, float jx, float jy, float jz, const Neq& n,
+                                               const ModelF& M, const ViscF& V) {
+  float P[6], A[6];
+  if (V.drive_chai) {
+    float rb[Q], rn[Q];
+    rates_with(M, 0.0f, rb);
+    static_for<Q>([&](auto ki) {
+      constexpr int k = ki;
+      rn[k] = is_nu_slot(k) ? 1.0f : 0.0f;
+    });
+    strain_chai(P_, drho, jx, jy, jz, rb, M.inv_rho0, P);
+    strain_chai(P_, drho, jx, jy, jz, rn, M.inv_rho0, A);
+  } else {
+    strain_yu(n, M.s[1], 0.0f, M.inv_rho0, P);
+    strain_yu(n, 0.0f, 1.0f, M.inv_rho0, A);
+  }
+  return implicit_smagorinsky(P, A, V.nu0, V.csmag2);
+}
+
+// The s_nu a strain query or the diagnostics take the strain with: the stored lagged rate,
+// the implicit rate of the state itself, or the constant rate.
+__device__ __forceinline__ float query_rate(const Pairs& P, float drho, float jx, float jy, float jz, const Neq& n,
+                                            const ModelF& M, const ViscF& V, const float* snu_f, unsigned self) {
+  if (V.kind == 3) return implicit_rate(P, drho, jx, jy, jz, n, M, V);
+  return snu_f ? snu_f[self] : M.s[9];
+}
+
 template <typename S, bool WALLS, bool ROWS>
 __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -59,26 +88,43 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
     jz = __builtin_fmaf(0.5f, Fz, jz);
   }
   const Neq n = noneq_moments(P, drho, jx, jy, jz, M.inv_rho0);
-  // strain of the incoming state with the rates of the previous collision (lagged s_nu)
-  const float snu_prev = io.snu ? io.snu[self] : M.s[9];
-  const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
-  const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
   float Syu[6], Sch[6];
-  if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
-  if (need_chai) {
-    float r[Q];
-    rates_with(M, snu_prev, r);
-    strain_chai(P, drho, jx, jy, jz, r, M.inv_rho0, Sch);
-  }
-  if (io.S_out) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
-  }
   float snu = M.s[9];
-  if (V.kind != 0) {
-    snu = viscous_rate(V.drive_chai ? strain_sq(Sch) : strain_sq(Syu), V);
-    io.snu[self] = snu;
+  if (V.kind == 3) {
+    // implicit coupling: the strain at the rate of this very collision
+    snu = implicit_rate(P, drho, jx, jy, jz, n, M, V);
+    if (io.S_out) {
+      if (io.emit == 2) {
+        float r[Q];
+        rates_with(M, snu, r);
+        strain_chai(P, drho, jx, jy, jz, r, M.inv_rho0, Sch);
+      } else {
+        strain_yu(n, M.s[1], snu, M.inv_rho0, Syu);
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
+    }
+  } else {
+    // lagged coupling: the strain of the incoming state with the rates of the previous collision
+    const float snu_prev = io.snu ? io.snu[self] : M.s[9];
+    const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
+    const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
+    if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
+    if (need_chai) {
+      float r[Q];
+      rates_with(M, snu_prev, r);
+      strain_chai(P, drho, jx, jy, jz, r, M.inv_rho0, Sch);
+    }
+    if (io.S_out) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
+    }
+    if (V.kind != 0) {
+      snu = viscous_rate(V.drive_chai ? strain_sq(Sch) : strain_sq(Syu), V);
+      io.snu[self] = snu;
+    }
   }
   // relaxation in moment space with the Guo term, then the back-transform
   float dm[Q];
@@ -106,8 +152,8 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
 }
 
 template <typename S>
-__global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
-                                                           int kind, float* S_out) {
+__global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* buf,
+                                                           const float* snu_f, int kind, float* S_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -120,14 +166,15 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Forc
   float Fx, Fy, Fz;
   load_force(Fo, G.N, nb.self, Fx, Fy, Fz);
   const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
-  const float snu = snu_f ? snu_f[nb.self] : M.s[9];
+  const Neq n = noneq_moments(P, drho, jx, jy, jz, M.inv_rho0);
+  const float snu = query_rate(P, drho, jx, jy, jz, n, M, V, snu_f, nb.self);
   float S6[6];
   if (kind == 2) {
     float r[Q];
     rates_with(M, snu, r);
     strain_chai(P, drho, jx, jy, jz, r, M.inv_rho0, S6);
   } else {
-    strain_yu(noneq_moments(P, drho, jx, jy, jz, M.inv_rho0), M.s[1], snu, M.inv_rho0, S6);
+    strain_yu(n, M.s[1], snu, M.inv_rho0, S6);
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) stream_store(&S_out[static_cast<size_t>(c) * G.N + nb.self], S6[c]);
@@ -200,8 +247,8 @@ __global__ __launch_bounds__(kMaxBlock) void set_kernel(Geo G, S* buf, const flo
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo, const S* buf, const float* snu_f,
-                                                     double* partials) {
+__global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* buf,
+                                                     const float* snu_f, double* partials) {
   double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
   // blocks take whole x-rows in turn; the threads of a block walk along the row
   const unsigned rows = static_cast<unsigned>(G.ny) * G.nz;
@@ -220,9 +267,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ForceF Fo,
       float Fx, Fy, Fz;
       load_force(Fo, G.N, nb.self, Fx, Fy, Fz);
       const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
+      const Neq n = noneq_moments(P, drho, jx, jy, jz, M.inv_rho0);
       float S6[6];
-      strain_yu(noneq_moments(P, drho, jx, jy, jz, M.inv_rho0), M.s[1], snu_f ? snu_f[nb.self] : M.s[9], M.inv_rho0,
-                S6);
+      strain_yu(n, M.s[1], query_rate(P, drho, jx, jy, jz, n, M, V, snu_f, nb.self), M.inv_rho0, S6);
       const double jj = static_cast<double>(jx) * jx + static_cast<double>(jy) * jy + static_cast<double>(jz) * jz;
       acc[0] += drho;
       acc[1] += jx;
@@ -271,13 +318,13 @@ hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& 
   return hipGetLastError();
 }
 
-hipError_t launch_strain(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
+hipError_t launch_strain(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const void* buf,
                          const float* snu, int kind, float* S_out, hipStream_t st) {
   const Launch L = node_launch(G);
   switch (storage) {
-    case 0: hipLaunchKernelGGL(strain_kernel<float>, L.grid, L.block, 0, st, G, M, Fo, cb<float>(buf), snu, kind, S_out); break;
-    case 1: hipLaunchKernelGGL(strain_kernel<_Float16>, L.grid, L.block, 0, st, G, M, Fo, cb<_Float16>(buf), snu, kind, S_out); break;
-    case 2: hipLaunchKernelGGL(strain_kernel<__bf16>, L.grid, L.block, 0, st, G, M, Fo, cb<__bf16>(buf), snu, kind, S_out); break;
+    case 0: hipLaunchKernelGGL(strain_kernel<float>, L.grid, L.block, 0, st, G, M, V, Fo, cb<float>(buf), snu, kind, S_out); break;
+    case 1: hipLaunchKernelGGL(strain_kernel<_Float16>, L.grid, L.block, 0, st, G, M, V, Fo, cb<_Float16>(buf), snu, kind, S_out); break;
+    case 2: hipLaunchKernelGGL(strain_kernel<__bf16>, L.grid, L.block, 0, st, G, M, V, Fo, cb<__bf16>(buf), snu, kind, S_out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -317,14 +364,14 @@ hipError_t launch_set(int storage, const Geo& G, void* buf, const float* canon, 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ForceF& Fo, const void* buf,
-                         const float* snu, double* partials, double* out, hipStream_t st) {
+hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo,
+                         const void* buf, const float* snu, double* partials, double* out, hipStream_t st) {
   unsigned nb = static_cast<unsigned>(G.ny) * G.nz;  // one x-row per block at a time
   if (nb > static_cast<unsigned>(kReduceBlocks)) nb = kReduceBlocks;
   switch (storage) {
-    case 0: hipLaunchKernelGGL(reduce_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, Fo, cb<float>(buf), snu, partials); break;
-    case 1: hipLaunchKernelGGL(reduce_kernel<_Float16>, dim3(nb), dim3(256), 0, st, G, M, Fo, cb<_Float16>(buf), snu, partials); break;
-    case 2: hipLaunchKernelGGL(reduce_kernel<__bf16>, dim3(nb), dim3(256), 0, st, G, M, Fo, cb<__bf16>(buf), snu, partials); break;
+    case 0: hipLaunchKernelGGL(reduce_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, cb<float>(buf), snu, partials); break;
+    case 1: hipLaunchKernelGGL(reduce_kernel<_Float16>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, cb<_Float16>(buf), snu, partials); break;
+    case 2: hipLaunchKernelGGL(reduce_kernel<__bf16>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, cb<__bf16>(buf), snu, partials); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

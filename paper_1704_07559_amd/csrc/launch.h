@@ -37,12 +37,12 @@ hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float*
                        const float* grad_u, hipStream_t);
 hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
                        hipStream_t);
-hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
-                         int kind, float* S_out, hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, int kind, float* S_out, hipStream_t);
 hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
 hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
-hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
-                         double* partials, double* out, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, double* partials, double* out, hipStream_t);
 }  // namespace d2q9
 
 namespace d3q15 {
@@ -50,12 +50,12 @@ hipError_t launch_init(int storage, const Geo&, const ModelF&, void* buf, float*
                        const float* grad_u, hipStream_t);
 hipError_t launch_step(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const StepIO&,
                        hipStream_t);
-hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
-                         int kind, float* S_out, hipStream_t);
+hipError_t launch_strain(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, int kind, float* S_out, hipStream_t);
 hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hipStream_t);
 hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
-hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ForceF&, const void* buf, const float* snu,
-                         double* partials, double* out, hipStream_t);
+hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
+                         const float* snu, double* partials, double* out, hipStream_t);
 }  // namespace d3q15
 
 hipError_t launch_reduce_final(const double* partials, int nblocks, double* out, hipStream_t);

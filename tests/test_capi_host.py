@@ -63,7 +63,10 @@ def test_size_limits_and_other_lattices():
     assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=capi.LBM_D3Q15, s=uneq)) == 0
     imp = capi.LBM_VISC_SMAGORINSKY_IMPLICIT
     assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=capi.LBM_D3Q15, s=s15,
-                                                 visc_kind=imp)) == 0
+                                                 visc_kind=imp)) == 15 * 4 * 120
+    s9 = [0.0, 1.6, 1.2, 0.0, 1.6, 0.0, 1.6, 1.25, 1.25] + [0.0] * 10
+    assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=1, lattice=capi.LBM_D2Q9, s=s9,
+                                                 visc_kind=imp)) == 9 * 4 * 30
     assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, s=s, visc_kind=imp)) == 19 * 4 * 120
     assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=7, s=s)) == 0
 

@@ -19,7 +19,7 @@ def _spec(shape, tau=0.8, s=None, visc="const", drive="yu", walls=False, force=N
     _, ny, nx = shape
     sv = od.default_rates(tau) if s is None else np.asarray(s, dtype=np.float64)
     op = od.Params(s=sv.copy(), visc_kind=visc, visc_strain=drive, walls_y=walls, force=force, **kw)
-    vk = {"const": 0, "smagorinsky": 1, "powerlaw": 2}[visc]
+    vk = {"const": 0, "smagorinsky": 1, "powerlaw": 2, "smagorinsky_implicit": 3}[visc]
     fvec, ft = (0.0, 0.0, 0.0), None
     if force is not None:
         F = np.asarray(force, dtype=np.float64)
@@ -57,6 +57,9 @@ CASES = {
     "powerlaw_chai_walls_force": dict(visc="powerlaw", drive="chai", K_pl=0.02, n_pl=0.6, walls=True,
                                       force=np.array([1e-5, 0.0])),
     "force_field": dict(force="field"),
+    "smag_implicit_yu": dict(visc="smagorinsky_implicit", drive="yu", nu0=0.002, c_smag=0.3),
+    "smag_implicit_chai_walls_force": dict(visc="smagorinsky_implicit", drive="chai", nu0=0.005, c_smag=0.2,
+                                           walls=True, force=np.array([1e-5, 0.0])),
 }
 
 
@@ -81,6 +84,9 @@ def test_steps_from_random_state(case):
         assert strain_rel_err(to_np(S), Sy) < 1e-4, n
         assert strain_rel_err(S_chai, Sc) < 1e-4, n
         assert _pop_err(to_np(sim.populations()), ref.g) < 1e-5, n
+    Sy = ref.strain("yu")
+    ss = float((Sy[0] ** 2 + Sy[1] ** 2 + 2 * Sy[2] ** 2).sum())
+    assert abs(sim.reduce()["ss"] - ss) < 1e-4 * ss
 
 
 def test_taylor_green_64_squared_800_steps():
