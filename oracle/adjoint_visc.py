@@ -104,6 +104,7 @@ def collision_jacobians_visc(g: np.ndarray, s_prev: np.ndarray | None, F: np.nda
     """Per-node derivatives of (g, s_prev, F) -> (g*, s_new):
     Jgg (M, 19, 19), JgF (M, 19, 3), Jgs (19, M) = dg*/ds_prev, and the rate's own
     ds_dg (M, 19), ds_dF (M, 3), ds_dsp (M,)."""
+    adj.require_uncorrected(p)
     M = g[0].size
     j, mneq, SF = local_moments(g, F, p)
     sp = None if s_prev is None else s_prev.reshape(M)
@@ -148,6 +149,7 @@ def adjoint_step_visc(lam_next: np.ndarray, lams_next: np.ndarray | None, g: np.
 def strain_loss_seed_visc(g: np.ndarray, s_prev: np.ndarray | None, F: np.ndarray, p: d.Params):
     """(J, dJ/dg, dJ/ds_prev or None, dJ/dF) for J = sum_x S:S of the final state, the strain
     taken at the model's rate (lagged field, or implicitly solved)."""
+    adj.require_uncorrected(p)
     shape = g.shape[1:]
     M = g[0].size
     j, mneq, _ = local_moments(g, F, p)

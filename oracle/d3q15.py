@@ -75,6 +75,7 @@ class Params:
     nu_max: float = 1.0
     walls_y: bool = False
     force: np.ndarray | None = None  # (3,) uniform or (3, nz, ny, nx)
+    force_corrected: bool = False  # strain from the force-corrected non-equilibrium part
 
     def force_field(self, shape) -> np.ndarray:
         if self.force is None:
@@ -139,6 +140,16 @@ def _contract_cc(M, rho0):
 
 def _sv(s, ndim):
     return s if s.ndim == ndim else s.reshape((Q,) + (1,) * (ndim - 1))
+
+
+def strain_nonequilibrium(m, meq, f_neq, j, F, p: Params):
+    """(m - m^eq, f - f^eq), or with ``p.force_corrected`` both plus half the Guo source
+    (T F-bar / 2 and F-bar / 2): the first-order Chapman-Enskog balance of the forced
+    collision, as for D3Q19."""
+    if not p.force_corrected:
+        return m - meq, f_neq
+    Fbar = guo_force_populations(j, F, p.rho0)
+    return m - meq + 0.5 * moments(Fbar), f_neq + 0.5 * Fbar
 
 
 def strain_chai(f_neq, s, rho0):
@@ -212,21 +223,21 @@ def collide(g, p: Params, s_nu_prev):
     drho, j = macroscopic(g, F)
     m = moments(g)
     meq = m_eq(drho, j, p.rho0)
-    f_neq = g - g_eq(drho, j, p.rho0)
+    mn, fn = strain_nonequilibrium(m, meq, g - g_eq(drho, j, p.rho0), j, F, p)
     if p.visc_kind == "smagorinsky_implicit":
         # non-lagged coupling: the strain uses the rate of this very collision
         def yu_of(sv):
-            return strain_yu_type(m - meq, rates_field(p, sv), p.rho0)
+            return strain_yu_type(mn, rates_field(p, sv), p.rho0)
 
         def chai_of(sv):
-            return strain_chai(f_neq, rates_field(p, sv), p.rho0)
+            return strain_chai(fn, rates_field(p, sv), p.rho0)
 
         s_nu = implicit_smagorinsky_rate(yu_of if p.visc_strain == "yu" else chai_of, p, g.shape[1:])
         S_yu, S_chai = yu_of(s_nu), chai_of(s_nu)
     else:
         sp = rates_field(p, s_nu_prev)
-        S_yu = strain_yu_type(m - meq, sp, p.rho0)
-        S_chai = strain_chai(f_neq, sp, p.rho0)
+        S_yu = strain_yu_type(mn, sp, p.rho0)
+        S_chai = strain_chai(fn, sp, p.rho0)
         s_nu = viscosity_rate(S_yu if p.visc_strain == "yu" else S_chai, p, float(p.s[9]))
     s = rates_field(p, s_nu)
     SF = moments(guo_force_populations(j, F, p.rho0))
@@ -258,9 +269,10 @@ def strain_of_state(g, p: Params, s_nu, kind="yu"):
     F = p.force_field(g.shape[1:])
     drho, j = macroscopic(g, F)
     s = rates_field(p, s_nu)
+    mn, fn = strain_nonequilibrium(moments(g), m_eq(drho, j, p.rho0), g - g_eq(drho, j, p.rho0), j, F, p)
     if kind == "yu":
-        return strain_yu_type(moments(g) - m_eq(drho, j, p.rho0), s, p.rho0)
-    return strain_chai(g - g_eq(drho, j, p.rho0), s, p.rho0)
+        return strain_yu_type(mn, s, p.rho0)
+    return strain_chai(fn, s, p.rho0)
 
 
 def ce_neq_moments(grad_u, p: Params, s_nu: float):

@@ -116,6 +116,7 @@ class Params:
     nu_max: float = 1.0
     walls_y: bool = False        # halfway bounce-back at y = -1/2 and y = ny - 1/2
     force: np.ndarray | None = None  # (3,) uniform or (3, nz, ny, nx) field
+    force_corrected: bool = False  # strain from the force-corrected non-equilibrium part
 
     def force_field(self, shape) -> np.ndarray:
         if self.force is None:
@@ -223,6 +224,23 @@ def strain_yu(m_neq: np.ndarray, s1, s9, rho0: float) -> np.ndarray:
     Syz = -3.0 * s9 * m_neq[14] / (2.0 * rho0)
     Sxz = -3.0 * s9 * m_neq[15] / (2.0 * rho0)
     return np.stack([Sxx, Syy, Szz, Sxy, Syz, Sxz])
+
+
+def strain_nonequilibrium(m: np.ndarray, meq: np.ndarray, f_neq: np.ndarray, j: np.ndarray, F: np.ndarray,
+                          p: Params):
+    """The non-equilibrium parts the two strain formulas take: (m - m^eq, f - f^eq), or, with
+    ``p.force_corrected``, (m - m^eq + T F-bar / 2, f - f^eq + F-bar / 2).
+
+    The correction (the force effect the paper attributes to Premnath et al., Section 1)
+    follows from the first-order Chapman-Enskog balance of the Guo-forced collision:
+    s_k (m_k^(1) + S_F,k / 2) equals the force-free gradient term, so the half source added
+    to the non-equilibrium moments removes the u F terms that the force puts into the
+    second-order moments. Both formulas get the same half source (in moment and in velocity
+    space), so their identity (Section 5.1) is kept."""
+    if not p.force_corrected:
+        return m - meq, f_neq
+    Fbar = guo_force_populations(j, F, p.rho0)
+    return m - meq + 0.5 * moments(Fbar), f_neq + 0.5 * Fbar
 
 
 def strain_chai(f_neq: np.ndarray, s: np.ndarray, rho0: float) -> np.ndarray:
@@ -341,21 +359,21 @@ def collide(g: np.ndarray, p: Params, s_nu_prev: np.ndarray) -> CollideOut:
     drho, j = macroscopic(g, F)
     m = moments(g)
     meq = m_eq(drho, j, p.rho0, p.omega_eps, p.omega_epsj, p.omega_xx)
-    f_neq = g - g_eq(drho, j, p.rho0)
+    mn, fn = strain_nonequilibrium(m, meq, g - g_eq(drho, j, p.rho0), j, F, p)
     if p.visc_kind == "smagorinsky_implicit":
         # non-lagged coupling: the strain uses the rate of this very collision
         def yu_of(sv):
-            return strain_yu(m - meq, float(p.s[1]), sv, p.rho0)
+            return strain_yu(mn, float(p.s[1]), sv, p.rho0)
 
         def chai_of(sv):
-            return strain_chai(f_neq, rates_field(p, sv), p.rho0)
+            return strain_chai(fn, rates_field(p, sv), p.rho0)
 
         s_nu = implicit_smagorinsky_rate(yu_of if p.visc_strain == "yu" else chai_of, p, shape)
         S_yu, S_chai = yu_of(s_nu), chai_of(s_nu)
     else:
         s_prev = rates_field(p, s_nu_prev)
-        S_yu = strain_yu(m - meq, s_prev[1], s_prev[9], p.rho0)
-        S_chai = strain_chai(f_neq, s_prev, p.rho0)
+        S_yu = strain_yu(mn, s_prev[1], s_prev[9], p.rho0)
+        S_chai = strain_chai(fn, s_prev, p.rho0)
         S_drive = S_yu if p.visc_strain == "yu" else S_chai
         s_nu = viscosity_rate(S_drive, p, float(p.s[9]))
     s = rates_field(p, s_nu)
@@ -395,10 +413,11 @@ def strain_of_state(g: np.ndarray, p: Params, s_nu: np.ndarray, kind: str = "yu"
     F = p.force_field(g.shape[1:])
     drho, j = macroscopic(g, F)
     s = rates_field(p, s_nu)
+    meq = m_eq(drho, j, p.rho0, p.omega_eps, p.omega_epsj, p.omega_xx)
+    mn, fn = strain_nonequilibrium(moments(g), meq, g - g_eq(drho, j, p.rho0), j, F, p)
     if kind == "yu":
-        meq = m_eq(drho, j, p.rho0, p.omega_eps, p.omega_epsj, p.omega_xx)
-        return strain_yu(moments(g) - meq, s[1], s[9], p.rho0)
-    return strain_chai(g - g_eq(drho, j, p.rho0), s, p.rho0)
+        return strain_yu(mn, s[1], s[9], p.rho0)
+    return strain_chai(fn, s, p.rho0)
 
 
 # ---------------------------------------------------------------------------------------
