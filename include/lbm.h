@@ -56,7 +56,7 @@ typedef enum {
   LBM_ENOMEM = -3,       /* device scratch allocation failed */
   LBM_ESTATE = -4,       /* call not valid in the context's state (e.g. no force field) */
   LBM_ENONFINITE = -5,   /* lbm_reduce found non-finite populations */
-  LBM_EUNSUPPORTED = -6  /* valid but not provided combination (e.g. D2Q9 adjoint) */
+  LBM_EUNSUPPORTED = -6  /* valid but not provided combination (e.g. the D2Q9 adjoint) */
 } lbm_status;
 
 typedef enum { LBM_D2Q9 = 9, LBM_D3Q15 = 15, LBM_D3Q19 = 19 } lbm_lattice;
@@ -91,6 +91,14 @@ typedef enum {
  *  walls_y    0: periodic in y. 1: halfway bounce-back walls at y = -1/2 and y = ny - 1/2.
  *  force[3]   uniform body force (Guo forcing, j = sum c g + F/2) used when
  *             force_field is NULL; force_field: device float[3*N] field, or NULL.
+ *  strain_force_correction  1: every strain the library computes (emitted by lbm_step,
+ *             lbm_strain, lbm_reduce, the strain driving the viscosity) takes the force-
+ *             corrected non-equilibrium part, m - m^eq + S_F/2 (Yu) or f - f^eq + F-bar/2
+ *             (Chai), S_F = T F-bar the Guo source in moment space. This is the force effect
+ *             Section 1 attributes to Premnath et al., obtained from the first-order
+ *             Chapman-Enskog balance of the forced collision; it removes the u F terms the
+ *             force puts into the second-order moments. No effect without a force. The adjoint
+ *             entry points reject it (LBM_EUNSUPPORTED). 0: the plain non-equilibrium part.
  */
 typedef struct {
   int lattice;       /* lbm_lattice */
@@ -105,7 +113,12 @@ typedef struct {
   double nu0, c_smag, K_pl, n_pl, nu_min, nu_max;
   double force[3];
   const float* force_field;
+  int strain_force_correction; /* 0 or 1, see above */
 } lbm_params;
+
+/* sizeof(lbm_params) as the library was built: a binding that mirrors the struct (ctypes,
+ * another language) checks its own layout against it before the first call. */
+size_t lbm_params_size(void);
 
 /* Bytes of one population buffer (Q * N * element size) for these parameters, or 0 if the
  * parameters are invalid. */
@@ -137,7 +150,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
  *               the strain (formula `strain_kind`) of that step's pre-collision state; after
  *               the call it holds the strain of the state at level n_end - 1.
  *  strain_kind  LBM_STRAIN_YU or LBM_STRAIN_CHAI (ignored when S_out is NULL).
- *  save         device float[nsteps*R*N] or NULL, R = lbm_save_planes(ctx) (D3Q19 only):
+ *  save         device float[nsteps*R*N] or NULL, R = lbm_save_planes(ctx) (D3Q19 without
+ *               the strain force correction; LBM_EUNSUPPORTED otherwise):
  *               step k writes at offset k*R*N the record its adjoint needs: planes 0..2 the
  *               momentum j = sum c g + F/2 its collision used; for a strain-dependent
  *               viscosity (R = 10) also planes 3..8, the non-equilibrium moments
@@ -148,11 +162,13 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
 lbm_status lbm_step(lbm_ctx* ctx, int nsteps, float* S_out, int strain_kind, float* save, void* stream);
 
 /* Planes per step of lbm_step's adjoint record: 3 (constant viscosity) or 10 (strain-dependent
- * viscosity); 0 for D2Q9 or a NULL context. */
+ * viscosity); 0 where the adjoint is not provided (D2Q9, D3Q15, the strain force correction)
+ * or for a NULL context. */
 int lbm_save_planes(const lbm_ctx* ctx);
 
 /* Planes of the adjoint state lam (each N floats): 19 (the populations), or 20 for the lagged
- * viscosity kinds, whose plane 19 is the adjoint of the s_nu field; 0 for D2Q9 or NULL. */
+ * viscosity kinds, whose plane 19 is the adjoint of the s_nu field; 0 where the adjoint is not
+ * provided (as lbm_save_planes) or for NULL. */
 int lbm_adjoint_planes(const lbm_ctx* ctx);
 
 /* Strain of the current pre-collision state by the Yu (Eq. LuoS) or Chai (Eq. ChaiS)

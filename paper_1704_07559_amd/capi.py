@@ -30,7 +30,7 @@ LBM_STRAIN_NONE, LBM_STRAIN_YU, LBM_STRAIN_CHAI = 0, 1, 2
 LBM_VISC_CONST, LBM_VISC_SMAGORINSKY, LBM_VISC_POWERLAW, LBM_VISC_SMAGORINSKY_IMPLICIT = 0, 1, 2, 3
 
 EXPORTED = (
-    "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_strain", "lbm_reduce", "lbm_get_populations",
+    "lbm_params_size", "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_strain", "lbm_reduce", "lbm_get_populations",
     "lbm_set_populations", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count",
     "lbm_set_step_count", "lbm_save_planes", "lbm_adjoint_planes", "lbm_adjoint_step", "lbm_adjoint_steps", "lbm_strain_loss_seed", "lbm_init_adjoint", "lbm_destroy",
     "lbm_status_string", "lbm_last_error",
@@ -50,12 +50,14 @@ class lbm_params(ctypes.Structure):
         ("n_pl", ctypes.c_double), ("nu_min", ctypes.c_double), ("nu_max", ctypes.c_double),
         ("force", ctypes.c_double * 3),
         ("force_field", ctypes.c_void_p),
+        ("strain_force_correction", ctypes.c_int),
     ]
 
 
 _vp = ctypes.c_void_p
 _ctx_p = ctypes.c_void_p
 _sig = {
+    "lbm_params_size": (ctypes.c_size_t, []),
     "lbm_population_bytes": (ctypes.c_size_t, [ctypes.POINTER(lbm_params)]),
     "lbm_init": (ctypes.c_int, [ctypes.POINTER(_ctx_p), ctypes.POINTER(lbm_params), _vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_step": (ctypes.c_int, [_ctx_p, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp]),
@@ -82,6 +84,9 @@ for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
     _f.argtypes = _args
+if _lib.lbm_params_size() != ctypes.sizeof(lbm_params):
+    raise ImportError(f"{_LIB_PATH}: lbm_params is {_lib.lbm_params_size()} bytes in the library, "
+                      f"{ctypes.sizeof(lbm_params)} in this binding; rebuild the library")
 
 
 class LBMError(RuntimeError):
@@ -144,6 +149,7 @@ class Params:
     nu_max: float = 1.0
     force: Sequence[float] = (0.0, 0.0, 0.0)
     force_field: object = None  # device tensor (3*N float32) or None
+    strain_force_correction: int = 0
 
     def to_c(self) -> lbm_params:
         p = lbm_params()
@@ -160,6 +166,7 @@ class Params:
         for a in range(3):
             p.force[a] = float(self.force[a])
         p.force_field = _ptr(self.force_field)
+        p.strain_force_correction = int(self.strain_force_correction)
         return p
 
     @property

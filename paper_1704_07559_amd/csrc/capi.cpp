@@ -103,6 +103,8 @@ lbm_status check_params(const lbm_params* p, int* Q, size_t* N) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->force[a])) return fail(LBM_EINVAL, "force must be finite");
   if (p->force_field && !aligned(p->force_field, 4)) return fail(LBM_EINVAL, "force_field must be 4-byte aligned");
+  if (p->strain_force_correction != 0 && p->strain_force_correction != 1)
+    return fail(LBM_EINVAL, "strain_force_correction must be 0 or 1");
   *Q = q;
   *N = n;
   return LBM_OK;
@@ -134,10 +136,12 @@ void fill_model(lbm_ctx* c) {
   if (p.force_field) c->F.mode = 2;
   else if (p.force[0] != 0.0 || p.force[1] != 0.0 || p.force[2] != 0.0) c->F.mode = 1;
   else c->F.mode = 0;
+  c->F.strain_corr = (c->F.mode != 0 && p.strain_force_correction) ? 1 : 0;
 }
 
-// The adjoint and its per-step record are provided for D3Q19.
-bool is_d3q19(const lbm_ctx* c) { return c->Q == 19; }
+// The adjoint and its per-step record are provided for D3Q19 with the plain (not
+// force-corrected) strain.
+bool has_adjoint(const lbm_ctx* c) { return c->Q == 19 && !c->p.strain_force_correction; }
 
 lbm_status check_ctx(const lbm_ctx* c) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
@@ -160,6 +164,8 @@ int adjoint_planes(const lbm_ctx* c) {
 }  // namespace
 
 extern "C" {
+
+size_t lbm_params_size(void) { return sizeof(lbm_params); }
 
 size_t lbm_population_bytes(const lbm_params* p) {
   int Q;
@@ -222,9 +228,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
   return LBM_OK;
 }
 
-int lbm_save_planes(const lbm_ctx* c) { return (c && is_d3q19(c)) ? save_planes(c->V) : 0; }
+int lbm_save_planes(const lbm_ctx* c) { return (c && has_adjoint(c)) ? save_planes(c->V) : 0; }
 
-int lbm_adjoint_planes(const lbm_ctx* c) { return (c && is_d3q19(c)) ? adjoint_planes(c) : 0; }
+int lbm_adjoint_planes(const lbm_ctx* c) { return (c && has_adjoint(c)) ? adjoint_planes(c) : 0; }
 
 lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float* save, void* stream) {
   lbm_status st = check_ctx(c);
@@ -234,8 +240,8 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
   if (S_out && strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
   if (save && !aligned(save, 4)) return fail(LBM_EINVAL, "save must be 4-byte aligned");
-  if (save && !is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 only");
-  const size_t rec_elems = static_cast<size_t>(is_d3q19(c) ? save_planes(c->V) : 0) * c->G.N;
+  if (save && !has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 without the strain force correction");
+  const size_t rec_elems = static_cast<size_t>(has_adjoint(c) ? save_planes(c->V) : 0) * c->G.N;
   const hipStream_t s = as_stream(stream);
   for (int n = 0; n < nsteps; ++n) {
     StepIO io;
@@ -365,7 +371,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const float* rec_n, const float* lam_in,
                             void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
   if ((st = check_field(rec_n, "rec_n")) != LBM_OK) return st;
   if ((st = check_field(lam_in, "lam_in")) != LBM_OK) return st;
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
@@ -384,7 +390,7 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int nsteps, const float* rec, float* la
                              void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   if ((st = check_field(rec, "rec")) != LBM_OK) return st;
   if ((st = check_field(lam_a, "lam_a")) != LBM_OK) return st;
@@ -417,7 +423,7 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int nsteps, const float* rec, float* la
 lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, double* J_host, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
   if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
   if (!J_host) return fail(LBM_EINVAL, "J_host is NULL");
@@ -439,7 +445,7 @@ lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, d
 lbm_status lbm_init_adjoint(lbm_ctx* c, const float* rho_u, const float* lam0, float* grad_u0, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!is_d3q19(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
   if ((st = check_field(rho_u, "rho_u")) != LBM_OK) return st;
   if ((st = check_field(lam0, "lam0")) != LBM_OK) return st;
   if ((st = check_field(grad_u0, "grad_u0")) != LBM_OK) return st;

@@ -33,6 +33,7 @@ struct ForceF {
   int mode;  // 0 none, 1 uniform, 2 field
   float F[3];
   const float* field;
+  int strain_corr;  // strains take the non-equilibrium part plus half the Guo source (mode != 0 only)
 };
 
 // Node coordinates of the three source positions along each axis, indexed by c + 1:

@@ -32,10 +32,63 @@ __device__ __forceinline__ void rates_with(const ModelF& M, float snu, float (&r
 
 __device__ __forceinline__ float strain_sq(const float (&S)[3]) { return S[0] * S[0] + S[1] * S[1] + 2.0f * S[2] * S[2]; }
 
+// The force-corrected strain (optional) takes the non-equilibrium part plus half the Guo
+// source, m - m^eq + S_F/2. StrainIn holds the moments the Yu-type formula reads (ns) and,
+// with CORR, h = S_F/2, which the Chai formula adds as the Yu-type contraction of h with the
+// same rates (the Chai contraction of F-bar/2 in moment space). Without CORR only the plain
+// moments are held.
+template <bool CORR>
+struct StrainIn {
+  Neq ns;
+  Neq h;
+};
+
+template <bool CORR>
+__device__ __forceinline__ StrainIn<CORR> strain_in(const Neq& n, const float (&SF)[Q]) {
+  StrainIn<CORR> si;
+  if constexpr (CORR) {
+    static_for<Q>([&](auto ki) {
+      constexpr int k = ki;
+      si.h.m[k] = 0.5f * SF[k];
+      si.ns.m[k] = n.m[k] + si.h.m[k];
+    });
+  } else {
+    si.ns = n;
+  }
+  return si;
+}
+
+// The read-only kernels take the corrected form always, with a zero source when the
+// correction is off.
+__device__ __forceinline__ StrainIn<true> strain_in_state(const Neq& n, float jx, float jy, float Fx, float Fy,
+                                                          const ModelF& M, const ForceF& Fo) {
+  float SF[Q];
+  if (Fo.strain_corr) {
+    force_moments(jx, jy, Fx, Fy, M.inv_rho0, SF);
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) SF[k] = 0.0f;
+  }
+  return strain_in<true>(n, SF);
+}
+
+template <bool CORR>
+__device__ __forceinline__ void strain_chai_in(const Pairs& P, float drho, float jx, float jy, const float (&rates)[Q],
+                                               const StrainIn<CORR>& si, float inv_rho0, float (&S)[3]) {
+  strain_chai(P, drho, jx, jy, rates, inv_rho0, S);
+  if constexpr (CORR) {
+    float Sh[3];
+    strain_yu(si.h, rates[1], rates[7], inv_rho0, Sh);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[c] += Sh[c];
+  }
+}
+
 // s_nu of the implicit Smagorinsky coupling at one node, from the formula V selects (both
 // are affine in s_nu: split into the part at the other rates and the s_nu rows).
-__device__ __forceinline__ float implicit_rate(const Pairs& P_, float drho, float jx, float jy, const Neq& n,
-                                               const ModelF& M, const ViscF& V) {
+template <bool CORR>
+__device__ __forceinline__ float implicit_rate(const Pairs& P_, float drho, float jx, float jy,
+                                               const StrainIn<CORR>& si, const ModelF& M, const ViscF& V) {
   float P[3], A[3];
   if (V.drive_chai) {
     float rb[Q], rn[Q];
@@ -44,24 +97,26 @@ __device__ __forceinline__ float implicit_rate(const Pairs& P_, float drho, floa
       constexpr int k = ki;
       rn[k] = is_nu_slot(k) ? 1.0f : 0.0f;
     });
-    strain_chai(P_, drho, jx, jy, rb, M.inv_rho0, P);
-    strain_chai(P_, drho, jx, jy, rn, M.inv_rho0, A);
+    strain_chai_in(P_, drho, jx, jy, rb, si, M.inv_rho0, P);
+    strain_chai_in(P_, drho, jx, jy, rn, si, M.inv_rho0, A);
   } else {
-    strain_yu(n, M.s[1], 0.0f, M.inv_rho0, P);
-    strain_yu(n, 0.0f, 1.0f, M.inv_rho0, A);
+    strain_yu(si.ns, M.s[1], 0.0f, M.inv_rho0, P);
+    strain_yu(si.ns, 0.0f, 1.0f, M.inv_rho0, A);
   }
   return implicit_smagorinsky(P, A, V.nu0, V.csmag2);
 }
 
 // The s_nu a strain query or the diagnostics take the strain with: the stored lagged rate,
 // the implicit rate of the state itself, or the constant rate.
-__device__ __forceinline__ float query_rate(const Pairs& P, float drho, float jx, float jy, const Neq& n,
+__device__ __forceinline__ float query_rate(const Pairs& P, float drho, float jx, float jy, const StrainIn<true>& si,
                                             const ModelF& M, const ViscF& V, const float* snu_f, unsigned self) {
-  if (V.kind == 3) return implicit_rate(P, drho, jx, jy, n, M, V);
+  if (V.kind == 3) return implicit_rate(P, drho, jx, jy, si, M, V);
   return snu_f ? snu_f[self] : M.s[7];
 }
 
-template <typename S, bool WALLS, bool ROWS>
+// CORR: the force-corrected strain (a separate instance, so that the plain step keeps its
+// register budget).
+template <typename S, bool WALLS, bool ROWS, bool CORR>
 __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -81,18 +136,23 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
     jy = __builtin_fmaf(0.5f, Fy, jy);
   }
   const Neq n = noneq_moments(P, drho, jx, jy, M.inv_rho0);
+  // the Guo source in moment space; with CORR formed before the strain (half of it joins the
+  // non-equilibrium part the strain takes)
+  float SF[Q];
+  if constexpr (CORR) force_moments(jx, jy, Fx, Fy, M.inv_rho0, SF);
+  const StrainIn<CORR> si = strain_in<CORR>(n, SF);
   float Syu[3], Sch[3];
   float snu = M.s[7];
   if (V.kind == 3) {
     // implicit coupling: the strain at the rate of this very collision
-    snu = implicit_rate(P, drho, jx, jy, n, M, V);
+    snu = implicit_rate(P, drho, jx, jy, si, M, V);
     if (io.S_out) {
       if (io.emit == 2) {
         float r[Q];
         rates_with(M, snu, r);
-        strain_chai(P, drho, jx, jy, r, M.inv_rho0, Sch);
+        strain_chai_in(P, drho, jx, jy, r, si, M.inv_rho0, Sch);
       } else {
-        strain_yu(n, M.s[1], snu, M.inv_rho0, Syu);
+        strain_yu(si.ns, M.s[1], snu, M.inv_rho0, Syu);
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c)
@@ -103,11 +163,11 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
     const float snu_prev = io.snu ? io.snu[self] : M.s[7];
     const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
     const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
-    if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
+    if (need_yu) strain_yu(si.ns, M.s[1], snu_prev, M.inv_rho0, Syu);
     if (need_chai) {
       float r[Q];
       rates_with(M, snu_prev, r);
-      strain_chai(P, drho, jx, jy, r, M.inv_rho0, Sch);
+      strain_chai_in(P, drho, jx, jy, r, si, M.inv_rho0, Sch);
     }
     if (io.S_out) {
 #pragma unroll
@@ -128,8 +188,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
     if constexpr (k != 0 && k != 3 && k != 5) dm[k] = -(is_nu_slot(k) ? snu : M.s[k]) * n.m[k];
   });
   if (Fo.mode) {
-    float SF[Q];
-    force_moments(jx, jy, Fx, Fy, M.inv_rho0, SF);
+    if constexpr (!CORR) force_moments(jx, jy, Fx, Fy, M.inv_rho0, SF);
     static_for<Q>([&](auto ki) {
       constexpr int k = ki;
       if constexpr (k != 0 && k != 3 && k != 5) {
@@ -157,14 +216,15 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Visc
   load_force(Fo, G.N, nb.self, Fx, Fy);
   const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy;
   const Neq n = noneq_moments(P, drho, jx, jy, M.inv_rho0);
-  const float snu = query_rate(P, drho, jx, jy, n, M, V, snu_f, nb.self);
+  const StrainIn<true> si = strain_in_state(n, jx, jy, Fx, Fy, M, Fo);
+  const float snu = query_rate(P, drho, jx, jy, si, M, V, snu_f, nb.self);
   float S3[3];
   if (kind == 2) {
     float r[Q];
     rates_with(M, snu, r);
-    strain_chai(P, drho, jx, jy, r, M.inv_rho0, S3);
+    strain_chai_in(P, drho, jx, jy, r, si, M.inv_rho0, S3);
   } else {
-    strain_yu(n, M.s[1], snu, M.inv_rho0, S3);
+    strain_yu(si.ns, M.s[1], snu, M.inv_rho0, S3);
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) stream_store(&S_out[static_cast<size_t>(c) * G.N + nb.self], S3[c]);
@@ -247,7 +307,8 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ViscF V, F
       const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy;
       const Neq n = noneq_moments(P, drho, jx, jy, M.inv_rho0);
       float S3[3];
-      strain_yu(n, M.s[1], query_rate(P, drho, jx, jy, n, M, V, snu_f, nb.self), M.inv_rho0, S3);
+      const StrainIn<true> si = strain_in_state(n, jx, jy, Fx, Fy, M, Fo);
+      strain_yu(si.ns, M.s[1], query_rate(P, drho, jx, jy, si, M, V, snu_f, nb.self), M.inv_rho0, S3);
       const double jj = static_cast<double>(jx) * jx + static_cast<double>(jy) * jy;
       acc[0] += drho;
       acc[1] += jx;
@@ -267,18 +328,25 @@ static const S* cb(const void* p) {
   return static_cast<const S*>(p);
 }
 
-template <typename S>
-static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+template <typename S, bool CORR>
+static void launch_step_c(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const StepIO& io) {
   // whole x-rows per block: every load may stream (see pull)
   const bool rows = static_cast<int>(L.block.x) >= G.nx;
   if (walls) {
-    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-    else hipLaunchKernelGGL((step_kernel<S, true, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, true, false, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
   } else {
-    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-    else hipLaunchKernelGGL((step_kernel<S, false, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, false, false, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
   }
+}
+
+template <typename S>
+static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+                          const ForceF& Fo, const StepIO& io) {
+  if (Fo.strain_corr) launch_step_c<S, true>(walls, L, st, G, M, V, Fo, io);
+  else launch_step_c<S, false>(walls, L, st, G, M, V, Fo, io);
 }
 
 hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,

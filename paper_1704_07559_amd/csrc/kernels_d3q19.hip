@@ -34,14 +34,15 @@ __global__ __launch_bounds__(kMaxBlock) void strain_kernel(Geo G, ModelF M, Visc
   jy += 0.5f * Fy;
   jz += 0.5f * Fz;
   const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
-  const float snu = V.kind == 3 ? implicit_rate(P, drho, jx, jy, jz, n, M, V) : (snu_f ? snu_f[nb.self] : M.s[9]);
+  const StrainIn<true> si = strain_in_state(n, jx, jy, jz, Fx, Fy, Fz, M, Fo);
+  const float snu = V.kind == 3 ? implicit_rate(P, drho, jx, jy, jz, si, M, V) : (snu_f ? snu_f[nb.self] : M.s[9]);
   float S6[6];
   if (kind == 2) {
     float r[Q];
     rates_with(M, snu, r);
-    strain_chai(P, drho, jx, jy, jz, r, M.inv_rho0, S6);
+    strain_chai_in(P, drho, jx, jy, jz, r, si, M.inv_rho0, S6);
   } else {
-    strain_yu(n, M.s[1], snu, M.inv_rho0, S6);
+    strain_yu(si.ns, M.s[1], snu, M.inv_rho0, S6);
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) stream_store(&S_out[static_cast<size_t>(c) * G.N + nb.self], S6[c]);
@@ -144,9 +145,10 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ViscF V, F
       jy += 0.5f * Fy;
       jz += 0.5f * Fz;
       const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
-      const float snu = V.kind == 3 ? implicit_rate(P, drho, jx, jy, jz, n, M, V) : (snu_f ? snu_f[nb.self] : M.s[9]);
+      const StrainIn<true> si = strain_in_state(n, jx, jy, jz, Fx, Fy, Fz, M, Fo);
+      const float snu = V.kind == 3 ? implicit_rate(P, drho, jx, jy, jz, si, M, V) : (snu_f ? snu_f[nb.self] : M.s[9]);
       float S6[6];
-      strain_yu(n, M.s[1], snu, M.inv_rho0, S6);
+      strain_yu(si.ns, M.s[1], snu, M.inv_rho0, S6);
       const double jj = static_cast<double>(jx) * jx + static_cast<double>(jy) * jy + static_cast<double>(jz) * jz;
       acc[0] += drho;
       acc[1] += jx;

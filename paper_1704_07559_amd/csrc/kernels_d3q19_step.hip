@@ -22,6 +22,7 @@ namespace d3q19 {
 // model, relaxation with the Guo term, back-transform. g holds the pulled pre-collision
 // populations on entry and the post-collision populations on exit; `self` is the node's
 // element offset in the fields.
+template <bool CORR>
 __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const Geo& G, const ModelF& M,
                                             const ViscF& V, const ForceF& Fo, const StepIO& io) {
   const Pairs P_ = make_pairs(g);
@@ -35,21 +36,26 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
     jz = __builtin_fmaf(0.5f, Fz, jz);
   }
   const Neq n = noneq_moments(P_, drho, jx, jy, jz, M);
+  // the Guo source in moment space (the relaxation's forcing term); with CORR it is formed
+  // here, before the strain, since half of it joins the non-equilibrium part
+  float SF[Q];
+  if constexpr (CORR) force_moments(jx, jy, jz, Fx, Fy, Fz, M.inv_rho0, SF);
+  const StrainIn<CORR> si = strain_in<CORR>(n, SF);
 
   float Syu[6], Sch[6];
   float snu = M.s[9];
   float s_strain;  // the s_nu this step's strain is taken with
   if (V.kind == 3) {
     // implicit coupling: the strain at the rate of this very collision
-    snu = implicit_rate(P_, drho, jx, jy, jz, n, M, V);
+    snu = implicit_rate(P_, drho, jx, jy, jz, si, M, V);
     s_strain = snu;
     if (io.S_out) {
       if (io.emit == 2) {
         float r[Q];
         rates_with(M, snu, r);
-        strain_chai(P_, drho, jx, jy, jz, r, M.inv_rho0, Sch);
+        strain_chai_in(P_, drho, jx, jy, jz, r, si, M.inv_rho0, Sch);
       } else {
-        strain_yu(n, M.s[1], snu, M.inv_rho0, Syu);
+        strain_yu(si.ns, M.s[1], snu, M.inv_rho0, Syu);
       }
 #pragma unroll
       for (int c = 0; c < 6; ++c)
@@ -61,11 +67,11 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
     s_strain = snu_prev;
     const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
     const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
-    if (need_yu) strain_yu(n, M.s[1], snu_prev, M.inv_rho0, Syu);
+    if (need_yu) strain_yu(si.ns, M.s[1], snu_prev, M.inv_rho0, Syu);
     if (need_chai) {
       float r[Q];
       rates_with(M, snu_prev, r);
-      strain_chai(P_, drho, jx, jy, jz, r, M.inv_rho0, Sch);
+      strain_chai_in(P_, drho, jx, jy, jz, r, si, M.inv_rho0, Sch);
     }
     if (io.S_out) {
 #pragma unroll
@@ -93,8 +99,7 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
     }
   });
   if (Fo.mode) {
-    float SF[Q];
-    force_moments(jx, jy, jz, Fx, Fy, Fz, M.inv_rho0, SF);
+    if constexpr (!CORR) force_moments(jx, jy, jz, Fx, Fy, Fz, M.inv_rho0, SF);
     static_for<Q>([&](auto ki) {
       constexpr int k = ki;
       if constexpr (k != 0 && k != 3 && k != 5 && k != 7 && k < 16) {
@@ -127,7 +132,9 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
 // ------------------------------------------------------------------------------------------
 // The fused step: one thread per node
 // ------------------------------------------------------------------------------------------
-template <typename S, bool WALLS, bool ROWS>
+// CORR: the force-corrected strain (a separate instance, so that the plain step keeps its
+// register budget).
+template <typename S, bool WALLS, bool ROWS, bool CORR>
 __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -136,22 +143,29 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   const Rows<Q, S> r = rows_of<Q, S>(G, x, y, z);
   float g[Q];
   pull_rows<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, r, y, g);
-  node_update(g, node_index(G, x, y, z), G, M, V, Fo, io);
+  node_update<CORR>(g, node_index(G, x, y, z), G, M, V, Fo, io);
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
+}
+
+template <typename S, bool CORR>
+static void launch_step_c(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+                          const ForceF& Fo, const StepIO& io) {
+  // whole x-rows per block: every load may stream (see pull)
+  const bool rows = static_cast<int>(L.block.x) >= G.nx;
+  if (walls) {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, true, false, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  } else {
+    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+    else hipLaunchKernelGGL((step_kernel<S, false, false, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  }
 }
 
 template <typename S>
 static void launch_step_t(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const StepIO& io) {
-  // whole x-rows per block: every load may stream (see pull)
-  const bool rows = static_cast<int>(L.block.x) >= G.nx;
-  if (walls) {
-    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-    else hipLaunchKernelGGL((step_kernel<S, true, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-  } else {
-    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-    else hipLaunchKernelGGL((step_kernel<S, false, false>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-  }
+  if (Fo.strain_corr) launch_step_c<S, true>(walls, L, st, G, M, V, Fo, io);
+  else launch_step_c<S, false>(walls, L, st, G, M, V, Fo, io);
 }
 
 hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const StepIO& io,

@@ -27,6 +27,8 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
     assert set(capi.EXPORTED) == set(_declared())
+    # the ctypes mirror of lbm_params has the library's layout
+    assert capi._lib.lbm_params_size() == ctypes.sizeof(capi.lbm_params)
 
 
 def test_population_bytes_and_validation():
@@ -38,6 +40,8 @@ def test_population_bytes_and_validation():
     assert capi.lbm_population_bytes(p) == 19 * 32 * 16 * 8 * 2
     bad = capi.Params(nx=0, ny=16, nz=8, s=s)
     assert capi.lbm_population_bytes(bad) == 0
+    assert capi.lbm_population_bytes(capi.Params(nx=32, ny=16, nz=8, s=s, strain_force_correction=1)) > 0
+    assert capi.lbm_population_bytes(capi.Params(nx=32, ny=16, nz=8, s=s, strain_force_correction=2)) == 0
     uneq = list(s)
     uneq[13] = 1.3
     assert capi.lbm_population_bytes(capi.Params(nx=4, ny=4, nz=4, s=uneq)) == 0
