@@ -21,6 +21,7 @@ adjoint      discrete adjoint of the D3Q19 step and of the strain-squared loss (
              viscosity)
 adjoint_visc the same for strain-dependent viscosities (lagged Smagorinsky and power law,
              implicit Smagorinsky)
+storage      round-to-nearest-even into binary16 / bfloat16 (the reduced-precision storage)
 closed_forms exact Navier-Stokes solutions used as expected values (Taylor-Green,
              power-law Poiseuille, start-up Poiseuille series)
 naive        a per-node pure-Python loop of the step for brute-force checks on tiny grids

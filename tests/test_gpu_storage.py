@@ -8,6 +8,10 @@ the measured errors are written to storage_errors*.json in the folder named by t
 environment variable LBM_RESULTS_DIR (when it is set), and the asserted bounds are a small
 multiple of what the storage rounding predicts: a half-ulp of the stored deviation per
 step, 2^-11 (FP16) or 2^-8 (BF16) relative, accumulated over the steps.
+
+The codec itself and a single step are exact: stored values equal the reference
+round-to-nearest-even of oracle/storage.py bit for bit, and a reduced-storage step equals the
+FP32-stored step rounded to the format.
 """
 import json
 import os
@@ -147,3 +151,72 @@ def test_storage_error_against_fp32_run_384_cubed():
             assert e["nonfinite"] == 0
             assert e["ke_rel_vs_f32"] < 500 * eps, (st, m, e)
             assert np.isfinite(e["dissipation_rel_vs_f32"]) and np.isfinite(e["spectrum_rel_vs_f32_energetic_k"])
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_codec_rounds_to_nearest_even(storage):
+    """Setting populations stores each value rounded to nearest even and reading widens it
+    exactly: bit-identical to the reference rounding, over many binades, exact ties and
+    FP16 subnormals, on a ragged box."""
+    import torch
+    from oracle import storage as ost
+    from paper_1704_07559_amd import lbm
+    shape = (3, 7, 65)
+    rng = np.random.default_rng(17)
+    x = (rng.normal(size=(19,) + shape) * 10.0 ** rng.uniform(-8, 3, size=(19,) + shape)).astype(np.float32)
+    # exact ties of the target format in the first plane
+    if storage == "f16":
+        b = rng.integers(1, 0x7BFF, size=x[0].size, dtype=np.uint16)
+        lo, hi = b.view(np.float16).astype(np.float64), (b + 1).view(np.float16).astype(np.float64)
+        x[0] = ((lo + hi) / 2).astype(np.float32).reshape(shape)
+    else:
+        hi16 = rng.integers(0x0080, 0x7F7F, size=x[0].size, dtype=np.uint32)
+        x[0] = ((hi16 << np.uint32(16)) | np.uint32(0x8000)).view(np.float32).reshape(shape)
+    _, cp, _ = spec_params(shape, storage=storage)
+    sim = lbm.LBM(cp)
+    sim.set_populations(torch.as_tensor(x).cuda())
+    got = sim.populations().cpu().numpy()
+    ref = ost.round_storage(x, storage)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), int((got != ref).sum())
+    sim.close()
+
+
+STEP_CASES = {
+    "const": dict(),
+    "smag_yu": dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2),
+    "implicit_chai_walls_force": dict(visc="smagorinsky_implicit", drive="chai", nu0=0.005, c_smag=0.3, walls=True,
+                                      force=np.array([1e-5, 0.0, 0.0])),
+}
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("case", sorted(STEP_CASES))
+def test_storage_changes_only_the_rounding(storage, case):
+    """From a state representable in the storage format, a step with reduced storage gives
+    the FP32-stored step's result rounded to nearest even, bit for bit, and the same strain:
+    the arithmetic is the same FP32 arithmetic, only the stored values are rounded. Three
+    steps, the FP32 run restarted each time from the reduced run's state."""
+    import torch
+    from oracle import storage as ost
+    from paper_1704_07559_amd import capi, lbm
+    shape = (4, 10, 69)
+    g0 = ost.round_storage(synth.random_state(19, shape, seed=11, scale=3e-3), storage)
+    _, c32, _ = spec_params(shape, **STEP_CASES[case])
+    _, cst, _ = spec_params(shape, storage=storage, **STEP_CASES[case])
+    a, b = lbm.LBM(c32), lbm.LBM(cst)
+    b.set_populations(torch.as_tensor(g0).cuda())
+    Sa, Sb = torch.empty((6,) + shape, device="cuda"), torch.empty((6,) + shape, device="cuda")
+    for n in range(3):
+        a.set_populations(b.populations())
+        if a.s_nu is not None:
+            a.s_nu.copy_(b.s_nu)
+        a.step(1, S_out=Sa, strain_kind=capi.LBM_STRAIN_CHAI)
+        b.step(1, S_out=Sb, strain_kind=capi.LBM_STRAIN_CHAI)
+        assert torch.equal(Sa, Sb), n
+        got = b.populations().cpu().numpy()
+        ref = ost.round_storage(a.populations().cpu().numpy(), storage)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (n, int((got != ref).sum()))
+        if a.s_nu is not None:
+            assert torch.equal(a.s_nu, b.s_nu), n
+    a.close()
+    b.close()
