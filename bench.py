@@ -199,23 +199,30 @@ def other_kernels(torch, np, synth, capi, lbm, u, steps, warmup):
     return out
 
 
-def copy_bandwidth(torch):
-    """Plain device-to-device copy of 1 GiB (read + write), for context."""
+def copy_bandwidth(torch, capi):
+    """Device-to-device copies of 1 GiB (1 GiB read + 1 GiB written), for context: the
+    library's STREAM-style copy kernel (16-byte nontemporal accesses; the practical ceiling
+    of a read-once/write-once pattern) and the runtime's own copy. GB/s of read + write."""
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / 1e3 / reps
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("stream_copy_GBps", lambda: capi.lbm_stream_copy(a, b, a.numel() * 4, stream)),
+                     ("runtime_copy_GBps", lambda: b.copy_(a))):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = round(2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3 / reps) / 1e9, 1)
+    assert torch.equal(a, b)
     del a, b
     torch.cuda.empty_cache()
-    return round(2 * (1 << 30) / t / 1e9, 1)
+    return out
 
 
 def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50, visc="const"):
@@ -469,7 +476,9 @@ def main():
                                                                 visc="smagorinsky")
         result["extra"]["other_kernels"] = other_kernels(torch, np, synth, capi, lbm, u, max(1, args.steps // 5),
                                                          args.warmup)
-        result["extra"]["copy_GBps"] = copy_bandwidth(torch)
+        cp = copy_bandwidth(torch, capi)
+        result["extra"].update(cp)
+        result["extra"]["step_over_stream_copy"] = round(result["roofline"]["achieved"] / cp["stream_copy_GBps"], 4)
 
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a slab")

@@ -246,6 +246,16 @@ lbm_status lbm_strain_loss_seed(lbm_ctx* ctx, float* lam_out, float* grad_force,
  */
 lbm_status lbm_init_adjoint(lbm_ctx* ctx, const float* rho_u, const float* lam0, float* grad_u0, void* stream);
 
+/*
+ * STREAM-style copy of `bytes` bytes from src to dst (device pointers, 16-byte aligned,
+ * bytes a multiple of 16, the ranges not overlapping), 16-byte nontemporal loads and stores,
+ * asynchronous on `stream`. A measurement aid, not part of the method: it gives the
+ * achievable HBM bandwidth of a pure streaming pattern on the device, the practical ceiling
+ * of the step kernel (whose algorithmic traffic is the same read-once/write-once streams).
+ * Errors: LBM_EINVAL (NULL, misaligned, overlapping, bytes not a multiple of 16), LBM_EHIP.
+ */
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 void lbm_destroy(lbm_ctx* ctx);
 const char* lbm_status_string(int status);
 const char* lbm_last_error(void);

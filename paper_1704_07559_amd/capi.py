@@ -33,7 +33,7 @@ EXPORTED = (
     "lbm_params_size", "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_strain", "lbm_reduce", "lbm_get_populations",
     "lbm_set_populations", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count",
     "lbm_set_step_count", "lbm_save_planes", "lbm_adjoint_planes", "lbm_adjoint_step", "lbm_adjoint_steps", "lbm_strain_loss_seed", "lbm_init_adjoint", "lbm_destroy",
-    "lbm_status_string", "lbm_last_error",
+    "lbm_status_string", "lbm_last_error", "lbm_stream_copy",
 )
 
 
@@ -77,6 +77,7 @@ _sig = {
     "lbm_strain_loss_seed": (ctypes.c_int, [_ctx_p, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "lbm_init_adjoint": (ctypes.c_int, [_ctx_p, _vp, _vp, _vp, _vp]),
     "lbm_destroy": (None, [_ctx_p]),
+    "lbm_stream_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
@@ -267,6 +268,10 @@ def lbm_init_adjoint(ctx: int, rho_u, lam0, grad_u0, stream=None):
 
 def lbm_destroy(ctx: int):
     _lib.lbm_destroy(ctx)
+
+
+def lbm_stream_copy(src, dst, nbytes: int, stream=None):
+    _check(_lib.lbm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)), "lbm_stream_copy")
 
 
 def lbm_status_string(status: int) -> str:

@@ -167,6 +167,17 @@ extern "C" {
 
 size_t lbm_params_size(void) { return sizeof(lbm_params); }
 
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst) return fail(LBM_EINVAL, "lbm_stream_copy: NULL pointer");
+  if (!aligned(src, 16) || !aligned(dst, 16) || bytes % 16 != 0)
+    return fail(LBM_EINVAL, "lbm_stream_copy: pointers and size must be multiples of 16 bytes");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+  if (a < b + bytes && b < a + bytes && bytes > 0) return fail(LBM_EINVAL, "lbm_stream_copy: ranges overlap");
+  const hipError_t e = launch_stream_copy(src, dst, bytes, as_stream(stream));
+  if (e != hipSuccess) return hip_fail(e, "lbm_stream_copy");
+  return LBM_OK;
+}
+
 size_t lbm_population_bytes(const lbm_params* p) {
   int Q;
   size_t N;

@@ -59,5 +59,6 @@ hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, c
 }  // namespace d3q15
 
 hipError_t launch_reduce_final(const double* partials, int nblocks, double* out, hipStream_t);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t);
 
 }  // namespace lbm

@@ -96,6 +96,17 @@ def test_init_rejects_bad_arguments_without_a_gpu():
         assert e.value.status == capi.LBM_EINVAL, capi.lbm_last_error()
 
 
+def test_stream_copy_rejects_bad_arguments_without_a_gpu():
+    """Validation of the copy runs before any HIP call (no launch happens here)."""
+    from paper_1704_07559_amd import capi
+    for src, dst, n in ((None, 1 << 24, 64), (1 << 20, None, 64), ((1 << 20) + 8, 1 << 24, 64),
+                        (1 << 20, (1 << 24) + 4, 64), (1 << 20, 1 << 24, 40), (1 << 20, (1 << 20) + 32, 64),
+                        ((1 << 20) + 32, 1 << 20, 64)):
+        with pytest.raises(capi.LBMError) as e:
+            capi.lbm_stream_copy(src, dst, n, stream=0)
+        assert e.value.status == capi.LBM_EINVAL, (src, dst, n)
+
+
 def test_status_strings():
     from paper_1704_07559_amd import capi
     assert capi.lbm_status_string(capi.LBM_OK) == "LBM_OK"

@@ -224,3 +224,17 @@ def test_adjoint_lam_aliasing_rejected():
     with pytest.raises(capi.LBMError) as e:
         capi.lbm_adjoint_step(sim.ctx, torch.zeros((3, N), device="cuda"), lam, lam)
     assert e.value.status == capi.LBM_EINVAL
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, 1 << 20, (1 << 22) + 4096 + 48])
+def test_stream_copy_is_exact(nbytes):
+    """The STREAM-style copy the benchmark uses for context copies every byte, and nothing
+    beyond the range (a guard region after the destination keeps its contents)."""
+    import torch
+    capi, _ = _lib()
+    src = torch.randint(-2**31, 2**31 - 1, (nbytes // 4,), dtype=torch.int32, device="cuda")
+    dst = torch.full((nbytes // 4 + 64,), 7, dtype=torch.int32, device="cuda")
+    capi.lbm_stream_copy(src, dst, nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[: nbytes // 4], src)
+    assert bool((dst[nbytes // 4:] == 7).all())
