@@ -433,6 +433,24 @@ def main():
                                        "kernel_ms": round(k3 * 1e3, 4), "bytes_per_node": bpn,
                                        "hbm_frac": round(bpn * m ** 3 / k3 / 1e9 / HBM_PEAK_GBS, 4),
                                        "ke": d3["ke"], "nonfinite": d3["nonfinite"]}
+        # one rank's share of a z-slab decomposition of the 384^3 FP16 run over 8 GPUs: the
+        # 384 x 384 x 48 interior, updated by the same kernel (its faces wrap periodically
+        # here; a decomposed run would read them from 2 ghost planes exchanged per step)
+        zs = m // 8
+        ps = les_params(capi, m, capi.LBM_F16)
+        ps.nz = zs
+        slab = rho_u3.reshape(4, m, m, m)[:, :zs].contiguous()
+        ss = lbm.LBM(ps, slab)
+        log(f"f16 {m}x{m}x{zs} slab: {args.warmup} warmup + {args.steps} timed steps")
+        wsl, ksl, dsl = time_run(ss, args.steps, args.warmup)
+        ss.close()
+        del ss, slab
+        halo = 2 * 5 * m * m * 2  # the 5 populations with c_z = +1 and the 5 with c_z = -1, FP16
+        extra["slab_384x384x48_f16"] = {"MLUPS": round(m * m * zs * args.steps / wsl / 1e6, 1),
+                                        "ms_per_step": round(wsl / args.steps * 1e3, 4),
+                                        "kernel_ms": round(ksl * 1e3, 4), "bytes_per_node": 84,
+                                        "hbm_frac": round(84 * m * m * zs / ksl / 1e9 / HBM_PEAK_GBS, 4),
+                                        "halo_bytes_per_step": halo, "nonfinite": dsl["nonfinite"]}
         del rho_u3
         torch.cuda.empty_cache()
         # the same 256^3 LES with the implicit (non-lagged) Smagorinsky coupling: no s_nu field
