@@ -75,6 +75,19 @@ def test_size_limits_and_other_lattices():
     assert capi.lbm_population_bytes(capi.Params(nx=6, ny=5, nz=4, lattice=7, s=s)) == 0
 
 
+def test_largest_boxes_sit_at_the_limit():
+    """The boxes of the maximum-size GPU tests are accepted, and one more row in y is not."""
+    from paper_1704_07559_amd import capi
+    from tests.test_gpu_maxsize import BOXES, _spec
+    for name, (q, storage, shape) in BOXES.items():
+        _, cp = _spec(q, shape, storage)
+        elem = 4 if storage == "f32" else 2
+        assert shape[1] * q * shape[2] * elem < 2 ** 32 <= (shape[1] + 1) * q * shape[2] * elem, name
+        assert capi.lbm_population_bytes(cp) == q * elem * shape[0] * shape[1] * shape[2], name
+        cp.ny += 1
+        assert capi.lbm_population_bytes(cp) == 0, name
+
+
 def test_init_rejects_bad_arguments_without_a_gpu():
     """Every case here fails validation, which runs before any HIP call or launch."""
     from paper_1704_07559_amd import capi
