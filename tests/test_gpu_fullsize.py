@@ -5,7 +5,7 @@ the whole field.
 
 * LES 256^3, FP32, Smagorinsky from the Yu strain (the headline workload);
 * power-law channel 128 x 128 x 512 with y-walls and a body force (Chai-driven viscosity);
-* LES 384^3 with FP16 storage (tolerance from the FP16 rounding of the stored deviation).
+* LES 384^3 with FP16 and BF16 storage (tolerance from the rounding of the stored deviation).
 """
 import numpy as np
 import pytest
@@ -94,14 +94,15 @@ def test_powerlaw_channel_128x128x512_sampled(n_pl):
 
 
 @pytest.mark.slow
-def test_les_384_cubed_fp16_sampled():
+@pytest.mark.parametrize("storage,eps", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_les_384_cubed_half_storage_sampled(storage, eps):
     shape = (384, 384, 384)
     u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
     kw = dict(tau=0.51, visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
-    wg, wS, ws, diag = _run(shape, u, "f16", kw, nsample=24, seed=2)
-    # FP16 keeps 11 significant bits of the stored deviation g (|g| < 0.4 f): a few
+    wg, wS, ws, diag = _run(shape, u, storage, kw, nsample=24, seed=2)
+    # FP16 keeps 11 significant bits of the stored deviation g, BF16 8 (|g| < 0.4 f): a few
     # half-ulps per step on f
-    assert wg < 4 * 2.0 ** -11, wg
+    assert wg < 4 * eps, wg
     assert diag["nonfinite"] == 0
 
 
