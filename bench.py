@@ -401,7 +401,7 @@ def main():
                    "nodes": N, "lattice": "D3Q19", "storage": "f32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "lbm::d3q19::step_kernel<float, false, true, false>",
+                     "traffic": traffic, "kernel": "lbm::d3q19::step_kernel<float, false, 2, false>",
                      "kernel_ms": round(kern * 1e3, 4), "bytes_per_node": bytes_per_node,
                      "kernel_source_sha": sha},
         "diagnostics": {"mass": diag["mass"], "ke": diag["ke"], "umax": diag["umax"], "nonfinite": diag["nonfinite"]},

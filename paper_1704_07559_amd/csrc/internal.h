@@ -181,6 +181,78 @@ __device__ __forceinline__ void pull_rows(const S* __restrict__ src, const Geo& 
   });
 }
 
+// The populations with c_x != 0 (the x-shifted ones) of a lattice: their number and the
+// LDS slot of each.
+template <class L>
+struct XShifted {
+  static constexpr int count() {
+    int n = 0;
+    for (int i = 0; i < L::Q; ++i) n += L::cx(i) != 0;
+    return n;
+  }
+  static constexpr int N = count();
+  static constexpr int slot(int i) {
+    int n = 0;
+    for (int k = 0; k < i; ++k) n += L::cx(k) != 0;
+    return n;
+  }
+};
+
+// Pull with the x-shifted populations exchanged through LDS, for blocks of whole rows:
+// blockDim.x == nx >= 64 (so at most 4 rows per 256-thread block) and every thread of the
+// block inside the box. Each thread loads its own aligned element of each x-shifted source
+// row into LDS; after one barrier it takes its neighbour's element (periodic within the row)
+// from there. Every global load is then aligned to the wave's segment, instead of the
+// x-shifted loads each touching one more cache line than they use. All threads of the block
+// must call it.
+template <class L, typename S, bool WALLS>
+__device__ __forceinline__ void pull_rows_staged(const S* __restrict__ src, const Geo& G, const Rows<L::Q, S>& r,
+                                                 int y, float (&g)[L::Q]) {
+  using X = XShifted<L>;
+  __shared__ float sh[X::N][256];
+  const char* cb = reinterpret_cast<const char*>(src);
+  const size_t run = static_cast<size_t>(G.nx) * sizeof(S);
+  const unsigned row = threadIdx.y * blockDim.x;
+  static_for<L::Q>([&](auto ii) {
+    constexpr int i = ii;
+    const char* base = cb + r.zb[L::cz(i) + 1] + i * run;
+    const unsigned off = r.yb[L::cy(i) + 1] + r.xb[1];
+    if constexpr (L::cx(i) != 0) {
+      sh[X::slot(i)][row + threadIdx.x] = load_at<S>(base, off);
+    } else {
+      if constexpr (WALLS && L::cy(i) != 0) {
+        if (crosses_wall<L::cy(i)>(G, y)) {
+          g[i] = load_at<S>(cb + r.zb[1] + L::opp(i) * run, r.self);
+          return;
+        }
+      }
+      g[i] = load_at<S>(base, off);
+    }
+  });
+  __syncthreads();
+  static_for<L::Q>([&](auto ii) {
+    constexpr int i = ii;
+    if constexpr (L::cx(i) != 0) {
+      if constexpr (WALLS && L::cy(i) != 0) {
+        if (crosses_wall<L::cy(i)>(G, y)) {
+          g[i] = load_at<S>(cb + r.zb[1] + L::opp(i) * run, r.self);
+          return;
+        }
+      }
+      g[i] = sh[X::slot(i)][row + r.xb[L::cx(i) + 1] / sizeof(S)];
+    }
+  });
+}
+
+// How a step launch pulls along x: 0 blocks hold part of a row (x-shifted loads cached, as
+// a neighbouring block reads their edge lines too); 1 blocks hold whole rows with masked
+// lanes (every load streams); 2 blocks hold whole rows exactly (LDS exchange above).
+inline int pull_mode(const Geo& G, const dim3& block) {
+  const int bx = static_cast<int>(block.x);
+  if (bx == G.nx && bx >= 64 && G.ny % static_cast<int>(block.y) == 0) return 2;
+  return bx >= G.nx ? 1 : 0;
+}
+
 // Inverse of pull_rows: write canonical g_i(x) to the internal slot it is pulled from.
 template <class L, typename S>
 __device__ __forceinline__ void scatter_rows(S* __restrict__ dst, const Geo& G, const Rows<L::Q, S>& r, int y,

@@ -114,9 +114,10 @@ __device__ __forceinline__ float query_rate(const Pairs& P, float drho, float jx
   return snu_f ? snu_f[self] : M.s[7];
 }
 
-// CORR: the force-corrected strain (a separate instance, so that the plain step keeps its
-// register budget).
-template <typename S, bool WALLS, bool ROWS, bool CORR>
+// XMODE: how a block pulls along x (pull_mode: 0 part rows, 1 whole rows, 2 whole rows with
+// the LDS exchange). CORR: the force-corrected strain (a separate instance, so that the plain
+// step keeps its register budget).
+template <typename S, bool WALLS, int XMODE, bool CORR>
 __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -125,7 +126,8 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   const unsigned self = node_index(G, x, y, 0);
   const Rows<Q, S> r = rows_of<Q, S>(G, x, y, 0);
   float g[Q];
-  pull_rows<Lat, S, WALLS, ROWS>(static_cast<const S*>(io.src), G, r, y, g);
+  if constexpr (XMODE == 2) pull_rows_staged<Lat, S, WALLS>(static_cast<const S*>(io.src), G, r, y, g);
+  else pull_rows<Lat, S, WALLS, XMODE == 1>(static_cast<const S*>(io.src), G, r, y, g);
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P);
@@ -331,14 +333,13 @@ static const S* cb(const void* p) {
 template <typename S, bool CORR>
 static void launch_step_c(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const StepIO& io) {
-  // whole x-rows per block: every load may stream (see pull)
-  const bool rows = static_cast<int>(L.block.x) >= G.nx;
-  if (walls) {
-    if (rows) hipLaunchKernelGGL((step_kernel<S, true, true, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-    else hipLaunchKernelGGL((step_kernel<S, true, false, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-  } else {
-    if (rows) hipLaunchKernelGGL((step_kernel<S, false, true, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
-    else hipLaunchKernelGGL((step_kernel<S, false, false, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io);
+  switch (pull_mode(G, L.block) + (walls ? 3 : 0)) {
+    case 0: hipLaunchKernelGGL((step_kernel<S, false, 0, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    case 1: hipLaunchKernelGGL((step_kernel<S, false, 1, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    case 2: hipLaunchKernelGGL((step_kernel<S, false, 2, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    case 3: hipLaunchKernelGGL((step_kernel<S, true, 0, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    case 4: hipLaunchKernelGGL((step_kernel<S, true, 1, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+    default: hipLaunchKernelGGL((step_kernel<S, true, 2, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
   }
 }
 

@@ -63,11 +63,13 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("shape", [(1, 23, 131), (1, 8, 128), (1, 5, 320)])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_steps_from_random_state(case):
+def test_steps_from_random_state(case, shape):
+    """Three steps from a far-from-equilibrium state; the shapes take the three ways a block
+    pulls along x (whole rows with masked lanes, whole rows through LDS, part rows)."""
     import torch
     from paper_1704_07559_amd import capi, lbm
-    shape = (1, 23, 131)
     kw = dict(CASES[case])
     if isinstance(kw.get("force"), str):
         kw["force"] = synth.uniform_random_force(shape, seed=5, amp=1e-4)[:2]

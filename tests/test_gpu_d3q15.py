@@ -63,13 +63,14 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("shape", [(7, 23, 131), (3, 8, 64), (2, 5, 192)])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_steps_from_random_state(case):
-    """Three steps from a far-from-equilibrium state on a ragged 7 x 23 x 131 box: the Yu-type
-    strain emitted by the step, the Chai strain queried before it, populations and s_nu."""
+def test_steps_from_random_state(case, shape):
+    """Three steps from a far-from-equilibrium state: the Yu-type strain emitted by the step,
+    the Chai strain queried before it, populations and s_nu. The shapes take the three ways a
+    block pulls along x (whole rows with masked lanes, whole rows through LDS, part rows)."""
     import torch
     from paper_1704_07559_amd import capi, lbm
-    shape = (7, 23, 131)
     kw = dict(CASES[case])
     if isinstance(kw.get("force"), str):
         kw["force"] = synth.uniform_random_force(shape, seed=5, amp=1e-4)

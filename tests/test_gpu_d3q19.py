@@ -72,13 +72,18 @@ CASES = {
 }
 
 
+# box shapes for the three ways a block pulls along x: whole rows with masked lanes (69),
+# whole rows exchanged through LDS (64: 4 rows of 64 per block), part rows (192: 64 wide)
+SHAPES = [(4, 10, 69), (3, 8, 64), (2, 5, 192)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_steps_from_random_state(case):
+def test_steps_from_random_state(case, shape):
     """A far-from-equilibrium random state (every moment non-zero), 3 steps; populations and
     both strain formulas (every step) against the oracle."""
     import torch
     capi, lbm = _lib()
-    shape = (4, 10, 69)
     kw = dict(CASES[case])
     if isinstance(kw.get("force"), str) and kw["force"] == "field":
         kw["force"] = synth.uniform_random_force(shape, seed=7559, amp=1e-4)
