@@ -244,6 +244,47 @@ __device__ __forceinline__ void pull_rows_staged(const S* __restrict__ src, cons
   });
 }
 
+// The structure-of-arrays counterpart of pull_rows_staged for node-indexed arrays (the
+// adjoint state): whole-row blocks, the x-shifted elements exchanged through LDS. All
+// threads of the block must call it.
+template <class L, typename S, bool WALLS>
+__device__ __forceinline__ void pull_staged(const S* __restrict__ src, const Geo& G, const Nbr& nb, int y,
+                                            float (&g)[L::Q]) {
+  using X = XShifted<L>;
+  __shared__ float sh[X::N][256];
+  const char* cb = reinterpret_cast<const char*>(src);
+  const size_t plane = static_cast<size_t>(G.N) * sizeof(S);
+  const unsigned row = threadIdx.y * blockDim.x;
+  static_for<L::Q>([&](auto ii) {
+    constexpr int i = ii;
+    const unsigned off = nb.zs[L::cz(i) + 1] + nb.ys[L::cy(i) + 1] + nb.xs[1];
+    if constexpr (L::cx(i) != 0) {
+      sh[X::slot(i)][row + threadIdx.x] = load_at<S>(cb + i * plane, off);
+    } else {
+      if constexpr (WALLS && L::cy(i) != 0) {
+        if (crosses_wall<L::cy(i)>(G, y)) {
+          g[i] = load_at<S>(cb + L::opp(i) * plane, nb.self);
+          return;
+        }
+      }
+      g[i] = load_at<S>(cb + i * plane, off);
+    }
+  });
+  __syncthreads();
+  static_for<L::Q>([&](auto ii) {
+    constexpr int i = ii;
+    if constexpr (L::cx(i) != 0) {
+      if constexpr (WALLS && L::cy(i) != 0) {
+        if (crosses_wall<L::cy(i)>(G, y)) {
+          g[i] = load_at<S>(cb + L::opp(i) * plane, nb.self);
+          return;
+        }
+      }
+      g[i] = sh[X::slot(i)][row + nb.xs[L::cx(i) + 1] / sizeof(S)];
+    }
+  });
+}
+
 // How a step launch pulls along x: 0 blocks hold part of a row (x-shifted loads cached, as
 // a neighbouring block reads their edge lines too); 1 blocks hold whole rows with masked
 // lanes (every load streams); 2 blocks hold whole rows exactly (LDS exchange above).

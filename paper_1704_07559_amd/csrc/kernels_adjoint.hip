@@ -143,7 +143,7 @@ __device__ __forceinline__ StrainParts strain_parts(const float (&mn)[6], float 
 // the collision rate s_new depends on the state: the record of the forward step holds j,
 // m^neq of rows 1, 9, 11, 13, 14, 15 and the strain's rate s_x; for the lagged kinds plane 19
 // of lam_in / lam_out is the adjoint of the s_nu field (not streamed).
-template <bool VISC>
+template <bool VISC, bool STAGE>
 __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, ViscF V, ForceF Fo,
                                                             const float* __restrict__ rec,
                                                             const float* __restrict__ lam_in,
@@ -159,7 +159,8 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, Vis
   const size_t N = G.N;
 
   float lt[Q];
-  pull<LatRev, float>(lam_in, G, nb, y, lt);
+  if constexpr (STAGE) pull_staged<LatRev, float, true>(lam_in, G, nb, y, lt);
+  else pull<LatRev, float>(lam_in, G, nb, y, lt);
 
   // mu = D^-1 T lam~
   const Pairs P = make_pairs(lt);
@@ -391,10 +392,15 @@ __global__ __launch_bounds__(kMaxBlock) void init_adjoint_kernel(Geo G, ModelF M
 hipError_t launch_adjoint_step(const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const float* rec,
                                const float* lam_in, float* lam_out, float* grad_force, hipStream_t st) {
   const Launch L = node_launch(G);
-  if (V.kind == 0)
-    hipLaunchKernelGGL(adjoint_kernel<false>, L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
-  else
-    hipLaunchKernelGGL(adjoint_kernel<true>, L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+  // whole-row blocks exchange the x-shifted adjoint elements through LDS (pull_mode 2)
+  const bool stage = pull_mode(G, L.block) == 2;
+  if (V.kind == 0) {
+    if (stage) hipLaunchKernelGGL((adjoint_kernel<false, true>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+    else hipLaunchKernelGGL((adjoint_kernel<false, false>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+  } else {
+    if (stage) hipLaunchKernelGGL((adjoint_kernel<true, true>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+    else hipLaunchKernelGGL((adjoint_kernel<true, false>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+  }
   return hipGetLastError();
 }
 

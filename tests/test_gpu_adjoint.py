@@ -26,11 +26,13 @@ def _state(shape, seed, p):
     return g.astype(np.float32).astype(np.float64)
 
 
+# (5, 9, 70): blocks of whole rows with masked lanes; (3, 8, 64): whole rows of 64, the
+# x-shifted adjoint elements exchanged through LDS
+@pytest.mark.parametrize("shape", [(5, 9, 70), (3, 8, 64)])
 @pytest.mark.parametrize("walls", [False, True])
-def test_adjoint_step_matches_oracle(walls):
+def test_adjoint_step_matches_oracle(walls, shape):
     import torch
     from paper_1704_07559_amd import capi, lbm
-    shape = (5, 9, 70)
     F = synth.uniform_random_force(shape, seed=3, amp=1e-4)
     op, cp, _ = spec_params(shape, tau=0.7, walls=walls, force=F)
     g = _state(shape, 1, op)

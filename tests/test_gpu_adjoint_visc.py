@@ -58,13 +58,13 @@ def _setup(name, shape, walls, seed):
     return op, cp, F, g, sp, sim
 
 
+@pytest.mark.parametrize("shape", [(5, 9, 70), (3, 8, 64)])
 @pytest.mark.parametrize("name,walls", [("smag_yu", False), ("smag_chai", True), ("powerlaw_thinning", True),
                                         ("powerlaw_thickening", False), ("implicit_yu", True),
                                         ("implicit_chai", False)])
-def test_adjoint_step_matches_oracle(name, walls):
+def test_adjoint_step_matches_oracle(name, walls, shape):
     import torch
     from paper_1704_07559_amd import capi
-    shape = (5, 9, 70)
     op, cp, F, g, sp, sim = _setup(name, shape, walls, 30)
     N = cp.N
     assert sim.save_planes == 10
