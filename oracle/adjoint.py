@@ -31,13 +31,6 @@ Q = d.Q
 # Exact derivatives of the quadratic building blocks
 # ---------------------------------------------------------------------------------------
 
-def require_uncorrected(p: d.Params) -> None:
-    """The adjoint differentiates the uncorrected strain; the force-corrected option is a
-    forward-only feature."""
-    if p.force_corrected:
-        raise NotImplementedError("the adjoint is not provided for the force-corrected strain")
-
-
 def dmeq_ddrho(p: d.Params) -> np.ndarray:
     """d m^eq / d delta_rho (m^eq is linear in delta_rho): shape (19,)."""
     z = np.zeros(3)
@@ -80,6 +73,18 @@ def dFbar_dF(j: np.ndarray, F: np.ndarray, p: d.Params) -> np.ndarray:
     return out
 
 
+def half_source_jacobians(j: np.ndarray, F: np.ndarray, p: d.Params):
+    """d h / d j and d h / d F, each (19, 3, M), of the half Guo source h = T F-bar / 2 that the
+    force-corrected strain adds to the non-equilibrium moments (both zero without the
+    correction): the strain input is X = T g - m^eq(delta_rho, j) + h(j, F)."""
+    M = j.shape[1]
+    if not p.force_corrected:
+        z = np.zeros((Q, 3, M))
+        return z, z
+    return (0.5 * np.einsum("ri,ikm->rkm", d.T, dFbar_dj(j, F, p)),
+            0.5 * np.einsum("ri,ikm->rkm", d.T, dFbar_dF(j, F, p)))
+
+
 def yu_map(p: d.Params, s_nu: float) -> np.ndarray:
     """The 6x19 linear map m^neq -> S of Eq. LuoS (columns = strain_yu of unit vectors)."""
     Y = np.empty((6, Q))
@@ -103,9 +108,9 @@ def collision_jacobians(g: np.ndarray, F: np.ndarray, p: d.Params, rates: np.nda
       dm*/dg = (I - L) T + L dm^eq/dg + (I - L/2) T dF-bar/dj C
       dm*/dF = L dm^eq/dj / 2 + (I - L/2) T (dF-bar/dF + dF-bar/dj / 2)
     with L = diag(s): the rates of p (constant viscosity), or ``rates`` (19, M) per node;
-    diagonal products are written as broadcasts.
+    diagonal products are written as broadcasts. (The strain, force-corrected or not, does
+    not enter the collision at fixed rates.)
     """
-    require_uncorrected(p)
     if rates is None and p.visc_kind != "const":
         raise ValueError("a strain-dependent viscosity needs the per-node rates")
     q, *shape = g.shape
@@ -181,10 +186,11 @@ def _with_force(p: d.Params, F: np.ndarray) -> d.Params:
 
 
 def strain_loss_seed(g: np.ndarray, F: np.ndarray, p: d.Params):
-    """(J, dJ/dg, dJ/dF) for J = sum_x S:S with S = Y (T g - m^eq(delta_rho, j)),
-    j = C g + F/2:  dJ/dg = (T - dm^eq/dg)^T Y^T (2 W S),  dJ/dF = -(dm^eq/dj)^T Y^T (2 W S) / 2,
+    """(J, dJ/dg, dJ/dF) for J = sum_x S:S with S = Y X, X = T g - m^eq(delta_rho, j) + h(j, F)
+    (h the half Guo source of the force-corrected strain, else 0), j = C g + F/2:
+      dJ/dg = (T - dm^eq/dg + dh/dj C)^T sigma,
+      dJ/dF = (-dm^eq/dj / 2 + dh/dj / 2 + dh/dF)^T sigma,   sigma = Y^T (2 W S),
     W = diag(1, 1, 1, 2, 2, 2)."""
-    require_uncorrected(p)
     q, *shape = g.shape
     M = int(np.prod(shape))
     gf = g.reshape(Q, M)
@@ -193,16 +199,23 @@ def strain_loss_seed(g: np.ndarray, F: np.ndarray, p: d.Params):
     j = d.C.astype(float) @ gf + 0.5 * Ff
     m = d.T @ gf
     meq = d.m_eq(drho, j, p.rho0, p.omega_eps, p.omega_epsj, p.omega_xx)
+    dhj, dhF = half_source_jacobians(j, Ff, p)
+    X = m - meq
+    if p.force_corrected:
+        X = X + 0.5 * (d.T @ d.guo_force_populations(j, Ff, p.rho0))
     Y = yu_map(p, float(p.s[9]))
-    S = Y @ (m - meq)
+    S = Y @ X
     W = np.array([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])
     J = float((W[:, None] * S * S).sum())
     sigma = Y.T @ (2.0 * W[:, None] * S)                       # (19, M) in moment space
     dmr = dmeq_ddrho(p)
     dmj = dmeq_dj(j, p)
     Cf = d.C.astype(float)
-    lam = d.T.T @ sigma - (np.ones((Q, 1)) * (dmr @ sigma)[None] + Cf.T @ np.einsum("rkm,rm->km", dmj, sigma))
-    gF = -0.5 * np.einsum("rkm,rm->km", dmj, sigma)
+    bj = np.einsum("rkm,rm->km", dmj, sigma)                   # (dm^eq/dj)^T sigma
+    hj = np.einsum("rkm,rm->km", dhj, sigma)                   # (dh/dj)^T sigma
+    hF = np.einsum("rkm,rm->km", dhF, sigma)                   # (dh/dF)^T sigma
+    lam = d.T.T @ sigma - np.ones((Q, 1)) * (dmr @ sigma)[None] + Cf.T @ (hj - bj)
+    gF = 0.5 * (hj - bj) + hF
     return J, lam.reshape(g.shape), gF.reshape((3,) + tuple(shape))
 
 

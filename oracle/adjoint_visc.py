@@ -11,7 +11,9 @@ adjoint of ``adjoint`` to the viscosity models of the forward oracle:
 gamma = |S| = sqrt(2 S:S). Eq. LuoS is affine in s_nu, so per node
   S(s) = (Y_e + s Y_n) m^neq,   m^neq = T g - m^eq(delta_rho, j),  j = C g + F/2,
 with Y_e the s_e part and Y_n the s_nu part at unit rate (the Chai strain is the same
-function, Section 5.1, so the derivative is taken on this form for either drive).
+function, Section 5.1, so the derivative is taken on this form for either drive). With the
+force-corrected strain, m^neq in S is replaced by X = m^neq + h, h = T F-bar / 2 the half
+Guo source, a bilinear function of (j, F) whose derivatives join the chain rule.
 
 The collision m* = m - L(s_new)(m - m^eq) + (I - L/2) T F-bar depends on (g, F) with the
 rates held fixed (``adjoint.collision_jacobians`` at the node's rates) and through s_new:
@@ -100,21 +102,36 @@ def rate_sensitivities(mneq: np.ndarray, s_prev: np.ndarray | None, p: d.Params)
     return s, ds_dm, dh * (dgdS * Am).sum(axis=0)
 
 
+def strain_input(mneq: np.ndarray, SF: np.ndarray, p: d.Params) -> np.ndarray:
+    """X, the moments the strain formulas take: m^neq, plus S_F / 2 for the force-corrected
+    strain."""
+    return mneq + 0.5 * SF if p.force_corrected else mneq
+
+
+def _chain_X(dv_dX: np.ndarray, j: np.ndarray, F: np.ndarray, p: d.Params):
+    """Per-node dv/dg (M, 19) and dv/dF (M, 3) of a quantity v with dv/dX (M, 19), through
+    X = T g - m^eq(delta_rho, j) + h(j, F), j = C g + F/2."""
+    Cf = d.C.astype(float)
+    dmj = adj.dmeq_dj(j, p)                                                # (19, 3, M)
+    dhj, dhF = adj.half_source_jacobians(j, F, p)
+    dXj = dhj - dmj                                                        # dX/dj
+    dX_dg = (d.T[None] - adj.dmeq_ddrho(p)[None, :, None] * np.ones((1, 1, Q))
+             + np.einsum("rkm,ki->mri", dXj, Cf))
+    dv_dg = np.einsum("mr,mri->mi", dv_dX, dX_dg)
+    dv_dF = np.einsum("mr,rkm->mk", dv_dX, 0.5 * dXj + dhF)
+    return dv_dg, dv_dF
+
+
 def collision_jacobians_visc(g: np.ndarray, s_prev: np.ndarray | None, F: np.ndarray, p: d.Params) -> dict:
     """Per-node derivatives of (g, s_prev, F) -> (g*, s_new):
     Jgg (M, 19, 19), JgF (M, 19, 3), Jgs (19, M) = dg*/ds_prev, and the rate's own
     ds_dg (M, 19), ds_dF (M, 3), ds_dsp (M,)."""
-    adj.require_uncorrected(p)
     M = g[0].size
     j, mneq, SF = local_moments(g, F, p)
     sp = None if s_prev is None else s_prev.reshape(M)
-    s, ds_dm, ds_dsp = rate_sensitivities(mneq, sp, p)
+    s, ds_dX, ds_dsp = rate_sensitivities(strain_input(mneq, SF, p), sp, p)
     Jgg, JgF = adj.collision_jacobians(g, F, p, rates=d.rates_field(p, s))
-    Cf = d.C.astype(float)
-    dmj = adj.dmeq_dj(j, p)                                                # (19, 3, M)
-    dmeq_dg = adj.dmeq_ddrho(p)[None, :, None] * np.ones((1, 1, Q)) + np.einsum("rkm,ki->mri", dmj, Cf)
-    ds_dg = np.einsum("mr,mri->mi", ds_dm, d.T[None] - dmeq_dg)           # m^neq = T g - m^eq
-    ds_dF = -0.5 * np.einsum("mr,rkm->mk", ds_dm, dmj)                    # j contains F/2
+    ds_dg, ds_dF = _chain_X(ds_dX, j, F.reshape(3, M), p)
     e_nu = np.zeros((Q, 1))
     e_nu[list(d.NU_SLOTS)] = 1.0
     dg_ds = d.TINV @ (-(mneq + 0.5 * SF) * e_nu)                           # (19, M)
@@ -149,17 +166,17 @@ def adjoint_step_visc(lam_next: np.ndarray, lams_next: np.ndarray | None, g: np.
 def strain_loss_seed_visc(g: np.ndarray, s_prev: np.ndarray | None, F: np.ndarray, p: d.Params):
     """(J, dJ/dg, dJ/ds_prev or None, dJ/dF) for J = sum_x S:S of the final state, the strain
     taken at the model's rate (lagged field, or implicitly solved)."""
-    adj.require_uncorrected(p)
     shape = g.shape[1:]
     M = g[0].size
-    j, mneq, _ = local_moments(g, F, p)
+    j, mneq, SF = local_moments(g, F, p)
+    X = strain_input(mneq, SF, p)
     Ye, Yn = strain_maps(p)
-    Am = Yn @ mneq
+    Am = Yn @ X
     if p.visc_kind == "smagorinsky_implicit":
-        s, ds_dm, _ = rate_sensitivities(mneq, None, p)
+        s, ds_dm, _ = rate_sensitivities(X, None, p)
     else:
         s = s_prev.reshape(M)
-    S = Ye @ mneq + s * Am
+    S = Ye @ X + s * Am
     J = float((W6[:, None] * S * S).sum())
     dJ_dS = 2.0 * W6[:, None] * S
     dJ_dm = Ye.T @ dJ_dS + s * (Yn.T @ dJ_dS)                              # (19, M)
@@ -169,11 +186,8 @@ def strain_loss_seed_visc(g: np.ndarray, s_prev: np.ndarray | None, F: np.ndarra
         dJ_dm = dJ_dm + ds_dm.T * dJ_ds
     else:
         lams = dJ_ds.reshape(shape)
-    Cf = d.C.astype(float)
-    dmj = adj.dmeq_dj(j, p)
-    b = np.einsum("rkm,rm->km", dmj, dJ_dm)
-    lam = d.T.T @ dJ_dm - (np.ones((Q, 1)) * (adj.dmeq_ddrho(p) @ dJ_dm)[None] + Cf.T @ b)
-    return J, lam.reshape(g.shape), lams, (-0.5 * b).reshape((3,) + shape)
+    lam, gF = _chain_X(dJ_dm.T, j, F.reshape(3, M), p)
+    return J, lam.T.reshape(g.shape), lams, gF.T.reshape((3,) + shape)
 
 
 def gradient_visc(u0: np.ndarray, F: np.ndarray, p: d.Params, nsteps: int, every: int | None = None):

@@ -9,7 +9,8 @@ Only the lattice tables (c, w, T) are shared. Autograd then differentiates it wi
 hand-written derivative, and J, dJ/du0 and dJ/dF must match oracle.adjoint.gradient to FP64
 resolution. The cases cover constant viscosity with walls and a force field, lagged
 Smagorinsky, the clamped power law with walls, and the implicit Smagorinsky coupling (here
-autograd runs through a converged Newton solve)."""
+autograd runs through a converged Newton solve), each also with the force-corrected strain
+(the strain takes the non-equilibrium part plus half the Guo source)."""
 import numpy as np
 import pytest
 import torch
@@ -107,24 +108,27 @@ def torch_loss(u0, F, p, nsteps):
         drho = g.sum(0)
         j = torch.einsum("ai,i...->a...", CC, g) + 0.5 * F
         geq = _geq(drho, j, p.rho0)
-        return j, geq, g - geq
+        fneq = g - geq
+        # what the strain takes: with the correction, plus half the Guo source
+        fs = fneq + 0.5 * _guo(j, F, p.rho0) if p.force_corrected else fneq
+        return j, geq, fs
 
     for _ in range(nsteps):
-        j, geq, fneq = state(g)
+        j, geq, fs = state(g)
         if p.visc_kind in ("smagorinsky", "powerlaw"):
-            snu = 1.0 / (3.0 * _nu(_strain(fneq, _rates(p.s, snu), p.rho0), p) + 0.5)
+            snu = 1.0 / (3.0 * _nu(_strain(fs, _rates(p.s, snu), p.rho0), p) + 0.5)
         elif p.visc_kind == "smagorinsky_implicit":
-            snu = _implicit(fneq, p)
+            snu = _implicit(fs, p)
         rates = _rates(p.s, snu)
         m = torch.einsum("ki,i...->k...", TT, g)
         meq = torch.einsum("ki,i...->k...", TT, geq)
         SF = torch.einsum("ki,i...->k...", TT, _guo(j, F, p.rho0))
         mpost = m - rates * (m - meq) + (1.0 - 0.5 * rates) * SF
         g = _stream(torch.einsum("ik,k...->i...", TI, mpost), p.walls_y)
-    j, geq, fneq = state(g)
+    j, geq, fs = state(g)
     if p.visc_kind == "smagorinsky_implicit":
-        snu = _implicit(fneq, p)
-    return _ss(_strain(fneq, _rates(p.s, snu), p.rho0)).sum()
+        snu = _implicit(fs, p)
+    return _ss(_strain(fs, _rates(p.s, snu), p.rho0)).sum()
 
 
 CASES = {
@@ -133,6 +137,12 @@ CASES = {
     "powerlaw_walls": dict(visc_kind="powerlaw", visc_strain="chai", K_pl=0.01, n_pl=0.6, nu_min=2e-3, nu_max=0.05,
                            walls_y=True),
     "smagorinsky_implicit": dict(visc_kind="smagorinsky_implicit", nu0=0.005, c_smag=0.4),
+    "const_walls_corrected": dict(walls_y=True, force_corrected=True),
+    "smagorinsky_corrected": dict(visc_kind="smagorinsky", nu0=0.01, c_smag=0.3, force_corrected=True),
+    "powerlaw_walls_corrected": dict(visc_kind="powerlaw", visc_strain="chai", K_pl=0.01, n_pl=0.6, nu_min=2e-3,
+                                     nu_max=0.05, walls_y=True, force_corrected=True),
+    "smagorinsky_implicit_corrected": dict(visc_kind="smagorinsky_implicit", nu0=0.005, c_smag=0.4,
+                                           force_corrected=True),
 }
 
 
@@ -150,7 +160,7 @@ def test_adjoint_matches_autograd(case):
     assert abs(Jt.item() - J) <= 1e-12 * J
     assert np.abs(ut.grad.numpy() - gu).max() <= 1e-9 * np.abs(gu).max()
     assert np.abs(Ft.grad.numpy() - gF).max() <= 1e-9 * np.abs(gF).max()
-    if case == "powerlaw_walls":
+    if case.startswith("powerlaw_walls"):
         # both branches occur in the last steps: nodes on the nu_max clamp (zero slope) and
         # nodes on the power law itself
         sim = d.Simulation(adj._with_force(p, F), d.init_populations(np.zeros(shape), u0, adj._with_force(p, F)))
