@@ -98,7 +98,7 @@ typedef enum {
  *             Section 1 attributes to Premnath et al., obtained from the first-order
  *             Chapman-Enskog balance of the forced collision; it removes the u F terms the
  *             force puts into the second-order moments. No effect without a force. The adjoint
- *             entry points reject it (LBM_EUNSUPPORTED). 0: the plain non-equilibrium part.
+ *             entry points differentiate it. 0: the plain non-equilibrium part.
  */
 typedef struct {
   int lattice;       /* lbm_lattice */
@@ -150,20 +150,20 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
  *               the strain (formula `strain_kind`) of that step's pre-collision state; after
  *               the call it holds the strain of the state at level n_end - 1.
  *  strain_kind  LBM_STRAIN_YU or LBM_STRAIN_CHAI (ignored when S_out is NULL).
- *  save         device float[nsteps*R*N] or NULL, R = lbm_save_planes(ctx) (D3Q19 without
- *               the strain force correction; LBM_EUNSUPPORTED otherwise):
+ *  save         device float[nsteps*R*N] or NULL, R = lbm_save_planes(ctx) (D3Q19 only;
+ *               LBM_EUNSUPPORTED otherwise):
  *               step k writes at offset k*R*N the record its adjoint needs: planes 0..2 the
  *               momentum j = sum c g + F/2 its collision used; for a strain-dependent
  *               viscosity (R = 10) also planes 3..8, the non-equilibrium moments
- *               m - m^eq of rows 1, 9, 11, 13, 14, 15 that enter Eq. LuoS, and plane 9, the
+ *               m - m^eq of rows 1, 9, 11, 13, 14, 15 that enter Eq. LuoS (plus S_F/2 with
+ *               strain_force_correction), and plane 9, the
  *               s_nu its strain was taken with (the lagged field value, or the implicitly
  *               solved rate).
  */
 lbm_status lbm_step(lbm_ctx* ctx, int nsteps, float* S_out, int strain_kind, float* save, void* stream);
 
 /* Planes per step of lbm_step's adjoint record: 3 (constant viscosity) or 10 (strain-dependent
- * viscosity); 0 where the adjoint is not provided (D2Q9, D3Q15, the strain force correction)
- * or for a NULL context. */
+ * viscosity); 0 where the adjoint is not provided (D2Q9, D3Q15) or for a NULL context. */
 int lbm_save_planes(const lbm_ctx* ctx);
 
 /* Planes of the adjoint state lam (each N floats): 19 (the populations), or 20 for the lagged

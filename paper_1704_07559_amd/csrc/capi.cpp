@@ -139,9 +139,8 @@ void fill_model(lbm_ctx* c) {
   c->F.strain_corr = (c->F.mode != 0 && p.strain_force_correction) ? 1 : 0;
 }
 
-// The adjoint and its per-step record are provided for D3Q19 with the plain (not
-// force-corrected) strain.
-bool has_adjoint(const lbm_ctx* c) { return c->Q == 19 && !c->p.strain_force_correction; }
+// The adjoint and its per-step record are provided for D3Q19.
+bool has_adjoint(const lbm_ctx* c) { return c->Q == 19; }
 
 lbm_status check_ctx(const lbm_ctx* c) {
   if (!c) return fail(LBM_EINVAL, "context is NULL");
@@ -251,7 +250,7 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
   if (S_out && strain_kind != LBM_STRAIN_YU && strain_kind != LBM_STRAIN_CHAI)
     return fail(LBM_EINVAL, "strain_kind must be LBM_STRAIN_YU or LBM_STRAIN_CHAI");
   if (save && !aligned(save, 4)) return fail(LBM_EINVAL, "save must be 4-byte aligned");
-  if (save && !has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 without the strain force correction");
+  if (save && !has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 only");
   const size_t rec_elems = static_cast<size_t>(has_adjoint(c) ? save_planes(c->V) : 0) * c->G.N;
   const hipStream_t s = as_stream(stream);
   for (int n = 0; n < nsteps; ++n) {
@@ -382,7 +381,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const float* rec_n, const float* lam_in,
                             void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
   if ((st = check_field(rec_n, "rec_n")) != LBM_OK) return st;
   if ((st = check_field(lam_in, "lam_in")) != LBM_OK) return st;
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
@@ -401,7 +400,7 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int nsteps, const float* rec, float* la
                              void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   if ((st = check_field(rec, "rec")) != LBM_OK) return st;
   if ((st = check_field(lam_a, "lam_a")) != LBM_OK) return st;
@@ -434,7 +433,7 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int nsteps, const float* rec, float* la
 lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, double* J_host, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
   if ((st = check_field(lam_out, "lam_out")) != LBM_OK) return st;
   if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
   if (!J_host) return fail(LBM_EINVAL, "J_host is NULL");
@@ -456,7 +455,7 @@ lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, d
 lbm_status lbm_init_adjoint(lbm_ctx* c, const float* rho_u, const float* lam0, float* grad_u0, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19 without the strain force correction");
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
   if ((st = check_field(rho_u, "rho_u")) != LBM_OK) return st;
   if ((st = check_field(lam0, "lam0")) != LBM_OK) return st;
   if ((st = check_field(grad_u0, "grad_u0")) != LBM_OK) return st;

@@ -111,6 +111,17 @@ __device__ __forceinline__ void meq_j_transpose(const YuT& y, float jx, float jy
   bz = (38.0f * jz * y.r1 - 2.0f * jz * y.r9 - 2.0f * jz * y.r11 + jy * y.r14 + jx * y.r15) * ir;
 }
 
+// (dh/du)^T y on rows 1, 9, 11, 13, 14, 15 for h = S_F / 2, the half Guo source the
+// force-corrected strain adds to the non-equilibrium moments. h is bilinear in u = j / rho0
+// and F and symmetric in the two, so with a = F this is the derivative along u and with
+// a = u the derivative along F.
+__device__ __forceinline__ void half_source_transpose(const YuT& y, float ax, float ay, float az, float& ox, float& oy,
+                                                      float& oz) {
+  ox = 19.0f * ax * y.r1 + 2.0f * ax * y.r9 + 0.5f * (ay * y.r13 + az * y.r15);
+  oy = 19.0f * ay * y.r1 - ay * y.r9 + ay * y.r11 + 0.5f * (ax * y.r13 + az * y.r14);
+  oz = 19.0f * az * y.r1 - az * y.r9 - az * y.r11 + 0.5f * (ay * y.r14 + ax * y.r15);
+}
+
 // Strain S = P + s A from the six non-equilibrium moments of Eq. LuoS: P the s_e part, A the
 // s_nu part at unit rate; gamma = |S| = sqrt(2 S:S) and dgamma/dS = 2 W S / gamma.
 struct StrainParts {
@@ -216,12 +227,14 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, Vis
   nu[5] += Ay + By;
   nu[7] += Az + Bz;
 
-  float gbx = 0.f, gby = 0.f, gbz = 0.f;  // extra dJ/dF through the rate
+  float gbx = 0.f, gby = 0.f, gbz = 0.f;  // extra dJ/dj through the rate
+  float hfx = 0.f, hfy = 0.f, hfz = 0.f;  // extra dJ/dF through the force-corrected strain
   if constexpr (VISC) {
     // sensitivity of J to this collision's rate: dm*_k/ds = -(m^neq_k + S_F,k / 2) on the
-    // s_nu rows, plus the adjoint of the s_nu field this collision writes (lagged kinds)
+    // s_nu rows, plus the adjoint of the s_nu field this collision writes (lagged kinds).
+    // With the force-corrected strain the record already holds m^neq + S_F / 2.
     float SF9 = 0.f, SF11 = 0.f, SF13 = 0.f, SF14 = 0.f, SF15 = 0.f;
-    if (Fo.mode) {
+    if (Fo.mode && !Fo.strain_corr) {
       SF9 = (4.0f * jx * Fx - 2.0f * jy * Fy - 2.0f * jz * Fz) * ir;
       SF11 = (2.0f * jy * Fy - 2.0f * jz * Fz) * ir;
       SF13 = (jx * Fy + jy * Fx) * ir;
@@ -249,6 +262,15 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, Vis
     // dJ/dm^neq = Y(s_x)^T d6; m^neq = m - m^eq(drho, j): (I - E)^T on it
     const YuT yv = yu_transpose(d6, M.s[1], sx, ir);
     meq_j_transpose(yv, jx, jy, jz, ir, gbx, gby, gbz);
+    if (Fo.strain_corr) {
+      // the strain's input also holds h(j, F) = S_F / 2
+      float hx, hy, hz;
+      half_source_transpose(yv, Fx, Fy, Fz, hx, hy, hz);
+      gbx -= hx * ir;
+      gby -= hy * ir;
+      gbz -= hz * ir;
+      half_source_transpose(yv, jx * ir, jy * ir, jz * ir, hfx, hfy, hfz);
+    }
     nu[0] += 11.0f * yv.r1;
     nu[1] += yv.r1;
     nu[9] += yv.r9;
@@ -273,9 +295,9 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, Vis
                       jy * v[12] + jx * v[13] + jz * v[14]) * ir + v[5] - (2.0f / 3.0f) * v[6];
     const float Cz = (38.0f * jz * v[1] - 11.0f * jz * v[2] - 2.0f * jz * v[9] + jz * v[10] - 2.0f * jz * v[11] +
                       jz * v[12] + jy * v[14] + jx * v[15]) * ir + v[7] - (2.0f / 3.0f) * v[8];
-    grad_force[self] += 0.5f * (Ax + Bx - gbx) + Cx;
-    grad_force[N + self] += 0.5f * (Ay + By - gby) + Cy;
-    grad_force[2 * N + self] += 0.5f * (Az + Bz - gbz) + Cz;
+    grad_force[self] += 0.5f * (Ax + Bx - gbx) + Cx + hfx;
+    grad_force[N + self] += 0.5f * (Ay + By - gby) + Cy + hfy;
+    grad_force[2 * N + self] += 0.5f * (Az + Bz - gbz) + Cz + hfz;
   }
 }
 
@@ -302,8 +324,19 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ViscF V
       float Fx, Fy, Fz;
       force_at(Fo, G.N, self, Fx, Fy, Fz);
       const float jx = momentum<0>(P) + 0.5f * Fx, jy = momentum<1>(P) + 0.5f * Fy, jz = momentum<2>(P) + 0.5f * Fz;
-      const Neq n = noneq_moments(P, drho, jx, jy, jz, M);
+      Neq n = noneq_moments(P, drho, jx, jy, jz, M);
       const float s1 = M.s[1], ir = M.inv_rho0;
+      if (Fo.strain_corr) {
+        // force-corrected strain: the moments the strain takes include S_F / 2
+        float SF[Q];
+        force_moments(jx, jy, jz, Fx, Fy, Fz, ir, SF);
+        n.m[1] += 0.5f * SF[1];
+        n.m[9] += 0.5f * SF[9];
+        n.m[11] += 0.5f * SF[11];
+        n.m[13] += 0.5f * SF[13];
+        n.m[14] += 0.5f * SF[14];
+        n.m[15] += 0.5f * SF[15];
+      }
       float sn = M.s[9];
       if (V.kind == 3) sn = implicit_rate_yu(n, M, V);
       else if (V.kind != 0) sn = snu_f[self];
@@ -346,17 +379,25 @@ __global__ __launch_bounds__(256) void loss_seed_kernel(Geo G, ModelF M, ViscF V
       float lam[Q];
       apply_transpose(sg, lam);
       const float a = -11.0f * sg[1];
-      float bx, by, bz;
+      float bx, by, bz, hfx = 0.f, hfy = 0.f, hfz = 0.f;
       meq_j_transpose(yv, jx, jy, jz, ir, bx, by, bz);
+      if (Fo.strain_corr) {
+        float hx, hy, hz;
+        half_source_transpose(yv, Fx, Fy, Fz, hx, hy, hz);
+        bx -= hx * ir;
+        by -= hy * ir;
+        bz -= hz * ir;
+        half_source_transpose(yv, jx * ir, jy * ir, jz * ir, hfx, hfy, hfz);
+      }
       static_for<Q>([&](auto ii) {
         constexpr int i = ii;
         lam[i] -= a + static_cast<float>(CX[i]) * bx + static_cast<float>(CY[i]) * by + static_cast<float>(CZ[i]) * bz;
       });
       store_local<Q>(lam_out, G, self * 4u, lam);
       if (grad_force) {
-        grad_force[self] -= 0.5f * bx;
-        grad_force[G.N + self] -= 0.5f * by;
-        grad_force[2 * static_cast<size_t>(G.N) + self] -= 0.5f * bz;
+        grad_force[self] += hfx - 0.5f * bx;
+        grad_force[G.N + self] += hfy - 0.5f * by;
+        grad_force[2 * static_cast<size_t>(G.N) + self] += hfz - 0.5f * bz;
       }
     }
   }

@@ -112,18 +112,18 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
 
   if (io.save) {
     // what the adjoint of this step needs: j, and for a strain-dependent viscosity the
-    // non-equilibrium moments entering Eq. LuoS and the rate the strain was taken with
+    // moments the strain took (Eq. LuoS rows; force-corrected when it is) and its rate
     const size_t N = G.N;
     stream_store(&io.save[self], jx);
     stream_store(&io.save[N + self], jy);
     stream_store(&io.save[2 * N + self], jz);
     if (V.kind != 0) {
-      stream_store(&io.save[3 * N + self], n.m[1]);
-      stream_store(&io.save[4 * N + self], n.m[9]);
-      stream_store(&io.save[5 * N + self], n.m[11]);
-      stream_store(&io.save[6 * N + self], n.m[13]);
-      stream_store(&io.save[7 * N + self], n.m[14]);
-      stream_store(&io.save[8 * N + self], n.m[15]);
+      stream_store(&io.save[3 * N + self], si.ns.m[1]);
+      stream_store(&io.save[4 * N + self], si.ns.m[9]);
+      stream_store(&io.save[5 * N + self], si.ns.m[11]);
+      stream_store(&io.save[6 * N + self], si.ns.m[13]);
+      stream_store(&io.save[7 * N + self], si.ns.m[14]);
+      stream_store(&io.save[8 * N + self], si.ns.m[15]);
       stream_store(&io.save[9 * N + self], s_strain);
     }
   }
