@@ -184,3 +184,25 @@ def test_les_256_cubed_d3q15_sampled():
             fr = max(fr, float(np.sqrt((wts * S_ref[k] ** 2).sum())))
     assert worst_g < 1e-5 and dS / fr < 1e-4, (worst_g, dS / fr)
     assert d["nonfinite"] == 0 and abs(d["mass"] - m0) < 1e-3
+
+
+@pytest.mark.parametrize("shape,walls", [((1, 1, 1), False), ((1, 2, 1), True), ((2, 1, 3), False), ((3, 2, 1), True)])
+def test_degenerate_boxes(shape, walls):
+    """Boxes one or two nodes wide along some axes (populations wrap onto the node itself or
+    its only neighbour): three steps with a force field and lagged Smagorinsky against the
+    oracle."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    F = synth.uniform_random_force(shape, seed=21, amp=1e-4)[:3]
+    op, cp = _spec(shape, walls=walls, force=F, visc="smagorinsky", drive="chai", nu0=0.01, c_smag=0.3)
+    sim = lbm.LBM(cp)
+    g0 = synth.random_state(15, shape, seed=22, scale=3e-3).astype(np.float32).astype(np.float64)
+    sim.set_populations(torch.as_tensor(g0.astype(np.float32)).cuda())
+    ref = od.Simulation(op, g0)
+    S = torch.empty((6,) + shape, device="cuda")
+    for n in range(3):
+        sim.step(1, S_out=S, strain_kind=capi.LBM_STRAIN_CHAI)
+        Sy, Sc = ref.step(1)
+        assert strain_rel_err(to_np(S), Sc) < 1e-4, n
+        assert _pop_err(to_np(sim.populations()), ref.g) < 1e-5, n
+    sim.close()

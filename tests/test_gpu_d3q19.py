@@ -243,3 +243,29 @@ def test_stream_copy_is_exact(nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst[: nbytes // 4], src)
     assert bool((dst[nbytes // 4:] == 7).all())
+
+
+@pytest.mark.parametrize("shape,walls", [((1, 1, 1), False), ((1, 2, 1), True), ((2, 1, 3), False),
+                                         ((1, 3, 2), True), ((5, 1, 1), False)])
+def test_degenerate_boxes(shape, walls):
+    """Boxes one or two nodes wide along some axes, where pulled populations wrap onto the node
+    itself or its only neighbour (and, with walls, both walls bound the same row): three
+    steps with a force field and lagged Smagorinsky against the oracle, and the reduction."""
+    import torch
+    capi, lbm = _lib()
+    F = synth.uniform_random_force(shape, seed=21, amp=1e-4)
+    op, cp, _ = spec_params(shape, walls=walls, force=F, visc="smagorinsky", drive="chai", nu0=0.01, c_smag=0.3)
+    sim = lbm.LBM(cp)
+    g0 = synth.random_state(19, shape, seed=22, scale=3e-3)
+    sim.set_populations(torch.as_tensor(g0.astype(np.float32)).cuda())
+    ref = od.Simulation(op, g0.astype(np.float32).astype(np.float64))
+    S = torch.empty((6,) + shape, device="cuda")
+    for n in range(3):
+        sim.step(1, S_out=S, strain_kind=capi.LBM_STRAIN_CHAI)
+        out = ref.step(1)
+        assert strain_rel_err(to_np(S), out.S_chai) < STRAIN_TOL, n
+        assert pop_rel_err(to_np(sim.populations()), ref.g, op.rho0) < POP_TOL, n
+    d, r = sim.reduce(), ref.diagnostics()
+    assert abs(d["mass"] - r["mass"]) < 1e-6 and np.abs(np.asarray(d["mom"]) - r["mom"]).max() < 1e-6
+    assert abs(d["ss"] - r["ss"]) < 1e-4 * r["ss"]
+    sim.close()
