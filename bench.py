@@ -12,7 +12,8 @@ non-finite watchdog) runs every 100 steps inside the timed region.
 Output: one JSON line. ``value`` is MLUPS (million lattice-node updates per second) with
 inputs resident in HBM. ``roofline`` prices the step kernel's algorithmic bytes per node
 (19 reads + 19 writes of 4 B, plus the 4 B read and write of the lagged s_nu field) against
-the 8 TB/s HBM peak, timed with HIP events around every launch on the stream it runs on.
+the 8 TB/s HBM peak, timed with HIP events around every 10th launch of the timed region on
+the stream it runs on (events on every launch would add their own gaps to the run).
 ``extra`` carries the FP16/BF16-stored 384^3 runs and their FP32 reference.
 ``cpu_baseline`` times the FP64 oracle on a bounded slab of the same workload.
 
@@ -91,35 +92,48 @@ def les_params(capi, n, storage):
                        nu0=(tau0 - 0.5) / 3.0, c_smag=0.1)
 
 
-def time_run(sim, steps, warmup, reduce_every=100, windows=None):
+def time_run(sim, steps, warmup, reduce_every=100, windows=None, sample_every=10):
     """Run warmup + timed steps; returns (wall seconds, mean kernel seconds, last diagnostics).
-    With ``windows`` = a list, it also receives the device time per step (ms) of each run of
-    ``reduce_every`` steps (events at the window edges, on the launch stream)."""
+    The diagnostics run every ``reduce_every`` steps inside the timed region without stalling
+    the stream (lbm_reduce_async into pinned host slots, one per check); every check is read
+    and verified once the run has finished. The kernel time is the mean over every
+    ``sample_every``-th launch of the timed region, each bracketed by HIP events on the launch
+    stream (events on every launch would add their own gaps to the run). With ``windows`` = a
+    list, it also receives the device time per step (ms) of each run of ``reduce_every``
+    steps (events at the window edges)."""
     import torch
     sim.step(warmup)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    edges = []
-    diag = None
+    sampled = list(range(0, steps, sample_every))
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
+    edge_ev = [torch.cuda.Event(enable_timing=True) for _ in range(0, steps, reduce_every)]
+    nchecks = steps // reduce_every
+    slots = torch.zeros((max(nchecks, 1), 8), dtype=torch.float64, pin_memory=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         if k % reduce_every == 0:
-            edges.append(ev[k][0])
-        ev[k][0].record()
-        sim.step(1)
-        ev[k][1].record()
+            edge_ev[k // reduce_every].record()
+        if k in ev:
+            ev[k][0].record()
+            sim.step(1)
+            ev[k][1].record()
+        else:
+            sim.step(1)
         if (k + 1) % reduce_every == 0:
-            diag = sim.reduce(allow_nonfinite=True)
+            sim.reduce_async(slots[(k + 1) // reduce_every - 1])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern = sum(a.elapsed_time(b) for a, b in ev) / steps / 1e3
+    kern = sum(a.elapsed_time(b) for a, b in ev.values()) / len(ev) / 1e3
     if windows is not None:
-        for a, b in zip(edges[:-1], edges[1:]):
+        for a, b in zip(edge_ev[:-1], edge_ev[1:]):
             windows.append(a.elapsed_time(b) / reduce_every)
-    if diag is None:
-        diag = sim.reduce(allow_nonfinite=True)
-    return wall, kern, diag
+    if nchecks == 0:
+        return wall, kern, sim.reduce(allow_nonfinite=True)
+    bad = [i for i in range(nchecks) if slots[i, 7].item() != 0.0]
+    if bad:
+        log(f"non-finite populations at check {bad[0]} ({(bad[0] + 1) * reduce_every} steps)")
+    return wall, kern, sim.diagnostics(slots[nchecks - 1].tolist())
 
 
 def channel_runs(torch, capi, lbm, steps, warmup):

@@ -32,7 +32,8 @@
  *     (a small reduction scratch) and none frees caller memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Every call is
  *     asynchronous on that stream, except where a host result is returned (lbm_reduce,
- *     lbm_strain_loss_seed), which synchronise the stream before returning.
+ *     lbm_strain_loss_seed), which synchronise the stream before returning
+ *     (lbm_reduce_async is the non-blocking form of lbm_reduce).
  *   - No C++ exception crosses the ABI. Every call returns an lbm_status; on failure
  *     lbm_last_error() gives a message (thread-local). Arguments are validated before any
  *     launch; a kernel-launch failure maps to LBM_EHIP.
@@ -184,6 +185,18 @@ lbm_status lbm_strain(lbm_ctx* ctx, int strain_kind, float* S_out, void* stream)
  * Synchronises the stream. Returns LBM_ENONFINITE (after filling host_out) if [7] > 0.
  */
 lbm_status lbm_reduce(lbm_ctx* ctx, double* host_out, void* stream);
+
+/*
+ * The same diagnostics without waiting: the two reduction passes and a copy of the 8
+ * doubles into `out` are queued on `stream` and the call returns at once. `out` is device
+ * memory or pinned (page-locked) host memory, 8-byte aligned; its values are valid once the
+ * stream has passed this point (an event or a later synchronisation). The non-finite count
+ * is not checked here: the caller reads out[7]. The reduction scratch belongs to the
+ * context, so reductions of one context must be ordered (one stream, or synchronised
+ * between streams). Lets a run keep the GPU busy while it monitors the state every k steps.
+ * Errors: LBM_EINVAL (NULL or misaligned out), LBM_EHIP.
+ */
+lbm_status lbm_reduce_async(lbm_ctx* ctx, double* out, void* stream);
 
 /* Current canonical pre-collision populations g_i(x, n) as FP32 (device float[Q*N]). */
 lbm_status lbm_get_populations(lbm_ctx* ctx, float* f_canon, void* stream);

@@ -33,7 +33,7 @@ EXPORTED = (
     "lbm_params_size", "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_strain", "lbm_reduce", "lbm_get_populations",
     "lbm_set_populations", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count",
     "lbm_set_step_count", "lbm_save_planes", "lbm_adjoint_planes", "lbm_adjoint_step", "lbm_adjoint_steps", "lbm_strain_loss_seed", "lbm_init_adjoint", "lbm_destroy",
-    "lbm_status_string", "lbm_last_error", "lbm_stream_copy",
+    "lbm_status_string", "lbm_last_error", "lbm_stream_copy", "lbm_reduce_async",
 )
 
 
@@ -63,6 +63,7 @@ _sig = {
     "lbm_step": (ctypes.c_int, [_ctx_p, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp]),
     "lbm_strain": (ctypes.c_int, [_ctx_p, ctypes.c_int, _vp, _vp]),
     "lbm_reduce": (ctypes.c_int, [_ctx_p, ctypes.POINTER(ctypes.c_double), _vp]),
+    "lbm_reduce_async": (ctypes.c_int, [_ctx_p, _vp, _vp]),
     "lbm_get_populations": (ctypes.c_int, [_ctx_p, _vp, _vp]),
     "lbm_set_populations": (ctypes.c_int, [_ctx_p, _vp, _vp]),
     "lbm_state_bytes": (ctypes.c_size_t, [_ctx_p]),
@@ -207,6 +208,12 @@ def lbm_reduce(ctx: int, stream=None, allow_nonfinite: bool = False):
     if not (allow_nonfinite and st == LBM_ENONFINITE):
         _check(st, "lbm_reduce")
     return list(out)
+
+
+def lbm_reduce_async(ctx: int, out, stream=None):
+    """Queue the diagnostics into ``out`` (8 float64: a device tensor or a pinned host
+    tensor); read it after the stream has passed this point."""
+    _check(_lib.lbm_reduce_async(ctx, _ptr(out), _stream(stream)), "lbm_reduce_async")
 
 
 def lbm_get_populations(ctx: int, f_canon, stream=None):

@@ -290,19 +290,46 @@ lbm_status lbm_strain(lbm_ctx* c, int strain_kind, float* S_out, void* stream) {
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_strain");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Queue both reduction passes of the diagnostics; the 8 results land in *dout (scratch).
+hipError_t queue_reduce(lbm_ctx* c, hipStream_t s, double** dout) {
+  double* partials = c->scratch;
+  *dout = c->scratch + static_cast<size_t>(kReduceBlocks) * kReduceVals;
+  switch (c->Q) {
+    case 19: return d3q19::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, *dout, s);
+    case 15: return d3q15::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, *dout, s);
+    default: return d2q9::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, *dout, s);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_reduce_async(lbm_ctx* c, double* out, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  if (!aligned(out, 8)) return fail(LBM_EINVAL, "out must be 8-byte aligned");
+  const hipStream_t s = as_stream(stream);
+  double* dout;
+  hipError_t e = queue_reduce(c, s, &dout);
+  if (e != hipSuccess) return hip_fail(e, "lbm_reduce_async");
+  e = hipMemcpyAsync(out, dout, sizeof(double) * kReduceVals, hipMemcpyDefault, s);
+  if (e != hipSuccess) return hip_fail(e, "lbm_reduce_async copy");
+  return LBM_OK;
+}
+
 lbm_status lbm_reduce(lbm_ctx* c, double* host_out, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
   if (!host_out) return fail(LBM_EINVAL, "host_out is NULL");
   const hipStream_t s = as_stream(stream);
-  double* partials = c->scratch;
-  double* dout = c->scratch + static_cast<size_t>(kReduceBlocks) * kReduceVals;
-  hipError_t e;
-  switch (c->Q) {
-    case 19: e = d3q19::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
-    case 15: e = d3q15::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
-    default: e = d2q9::launch_reduce(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->snu, partials, dout, s); break;
-  }
+  double* dout;
+  hipError_t e = queue_reduce(c, s, &dout);
   if (e != hipSuccess) return hip_fail(e, "lbm_reduce");
   e = hipMemcpyAsync(host_out, dout, sizeof(double) * kReduceVals, hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return hip_fail(e, "lbm_reduce copy");

@@ -85,7 +85,17 @@ class LBM:
         torch.cuda.current_stream().synchronize()
 
     def reduce(self, allow_nonfinite: bool = False) -> dict:
-        v = capi.lbm_reduce(self.ctx, allow_nonfinite=allow_nonfinite)
+        return self.diagnostics(capi.lbm_reduce(self.ctx, allow_nonfinite=allow_nonfinite))
+
+    def reduce_async(self, out: torch.Tensor) -> torch.Tensor:
+        """Queue the diagnostics into ``out`` (8 float64, on the device or pinned host memory)
+        without waiting; ``diagnostics(out)`` reads them once the stream has passed."""
+        capi.lbm_reduce_async(self.ctx, out)
+        return out
+
+    @staticmethod
+    def diagnostics(v) -> dict:
+        v = [float(a) for a in v]
         return {"mass": v[0], "mom": np.array(v[1:4]), "ke": v[4], "ss": v[5], "umax": v[6], "nonfinite": int(v[7])}
 
     def save_state(self) -> torch.Tensor:

@@ -120,6 +120,13 @@ def test_stream_copy_rejects_bad_arguments_without_a_gpu():
         assert e.value.status == capi.LBM_EINVAL, (src, dst, n)
 
 
+def test_reduce_async_rejects_bad_arguments_without_a_gpu():
+    from paper_1704_07559_amd import capi
+    for ctx, out in ((None, 1 << 20), (1 << 12, None), (1 << 12, (1 << 20) + 4)):
+        st = capi._lib.lbm_reduce_async(ctx, out, None)
+        assert st == capi.LBM_EINVAL, (ctx, out, st)
+
+
 def test_status_strings():
     from paper_1704_07559_amd import capi
     assert capi.lbm_status_string(capi.LBM_OK) == "LBM_OK"

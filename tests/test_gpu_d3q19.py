@@ -269,3 +269,36 @@ def test_degenerate_boxes(shape, walls):
     assert abs(d["mass"] - r["mass"]) < 1e-6 and np.abs(np.asarray(d["mom"]) - r["mom"]).max() < 1e-6
     assert abs(d["ss"] - r["ss"]) < 1e-4 * r["ss"]
     sim.close()
+
+
+def test_reduce_async_matches_reduce():
+    """The non-blocking diagnostics give the blocking call's bits, into pinned host memory
+    and into device memory, also when queued between steps and read afterwards."""
+    import torch
+    capi, lbm = _lib()
+    shape = (6, 10, 64)
+    dr, u, grad = _smooth_fields(shape, 31)
+    op, cp, _ = spec_params(shape, visc="smagorinsky", nu0=0.01, c_smag=0.2)
+    sim = lbm.LBM(cp, lbm.rho_u_field(dr, u), lbm.grad_field(grad))
+    host = torch.zeros((3, 8), dtype=torch.float64, pin_memory=True)
+    dev = torch.zeros((3, 8), dtype=torch.float64, device="cuda")
+    ref = []
+    for k in range(3):
+        sim.step(2)
+        sim.reduce_async(host[k])
+        sim.reduce_async(dev[k])
+        torch.cuda.current_stream().synchronize()
+        ref.append(capi.lbm_reduce(sim.ctx))
+    for k in range(3):
+        assert host[k].tolist() == ref[k]
+        assert dev[k].cpu().tolist() == ref[k]
+    # queued between steps, read only at the end
+    a = lbm.LBM(cp, lbm.rho_u_field(dr, u), lbm.grad_field(grad))
+    slots = torch.zeros((3, 8), dtype=torch.float64, pin_memory=True)
+    for k in range(3):
+        a.step(2)
+        a.reduce_async(slots[k])
+    torch.cuda.current_stream().synchronize()
+    assert [slots[k].tolist() for k in range(3)] == ref
+    sim.close()
+    a.close()
