@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="edge of the cubic LES box (default 256)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 384^3 FP16/BF16/FP32 storage runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--storage-probe", choices=("f16", "bf16", "f32"),
+                    help="only step the 384^3 LES in that storage (--steps steps; counter collection)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -377,6 +379,19 @@ def main():
 
     import synth
     from paper_1704_07559_amd import capi, lbm
+
+    if args.storage_probe:
+        m = 384
+        st = {"f16": capi.LBM_F16, "bf16": capi.LBM_BF16, "f32": capi.LBM_F32}[args.storage_probe]
+        u3 = synth.spectrum_velocity((m, m, m), seed=1704, u_rms=0.04)
+        sim = lbm.LBM(les_params(capi, m, st), lbm.rho_u_field(np.zeros((m, m, m)), u3))
+        del u3
+        sim.step(args.warmup + args.steps)
+        d = sim.reduce(allow_nonfinite=True)
+        sim.close()
+        print(json.dumps({"storage_probe": args.storage_probe, "steps": args.warmup + args.steps,
+                          "nonfinite": d["nonfinite"]}))
+        return
 
     n = args.n
     log(f"generating the {n}^3 initial field")
