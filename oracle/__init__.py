@@ -25,4 +25,5 @@ storage      round-to-nearest-even into binary16 / bfloat16 (the reduced-precisi
 closed_forms exact Navier-Stokes solutions used as expected values (Taylor-Green,
              power-law Poiseuille, start-up Poiseuille series)
 naive        a per-node pure-Python loop of the step for brute-force checks on tiny grids
+naive_other  the same per-node loop for D2Q9 and D3Q15 (closed-form Yu-type formulas)
 """
