@@ -143,41 +143,134 @@ __device__ __forceinline__ Pairs make_pairs(const float (&g)[Q]) {
   return P;
 }
 
-// m_k = sum_i T_ki g_i, for a row of either parity.
+// ---------------------------------------------------------------------------------------
+// Factored transforms. The rows of T share partial sums of the pair sums and differences:
+// the density, e and eps rows see only g_0, the sum over the six axis directions and the
+// sum over the twelve diagonal ones; the stress rows see the axis pair sums and the sums of
+// the diagonal pairs per coordinate plane; the momentum, heat-flux and ghost rows see the
+// differences of the diagonal pairs per plane. Sharing them cuts the transform arithmetic
+// to about a third of row-by-row evaluation. Written once for any arithmetic type, so that
+// the compile-time check below runs them on unit vectors against T itself.
+// Pair order (DV.pa): (1,2) (3,4) (5,6) (7,10) (8,9) (11,14) (12,13) (15,18) (16,17).
+// ---------------------------------------------------------------------------------------
+template <typename F>
+__host__ __device__ constexpr void forward_transform(F g0, const F (&s)[NP], const F (&d)[NP], F (&m)[Q]) {
+  // even rows, from the pair sums
+  const F A = s[3] + s[4];  // diagonals in the xy plane
+  const F B = s[5] + s[6];  // xz plane
+  const F C = s[7] + s[8];  // yz plane
+  const F AB = A + B;
+  const F Sdg = AB + C;  // all twelve diagonals
+  const F s12 = s[1] + s[2];
+  const F Sax = s[0] + s12;  // all six axis directions
+  m[0] = (g0 + Sax) + Sdg;
+  m[1] = F(-30) * g0 + (F(-11) * Sax + F(8) * Sdg);
+  m[2] = F(12) * g0 + (F(-4) * Sax + Sdg);
+  const F T1 = F(-2) * C + AB;
+  m[9] = (F(2) * s[0] + T1) - s12;
+  m[10] = F(-4) * s[0] + (F(2) * s12 + T1);
+  const F D12 = s[1] - s[2];
+  const F AmB = A - B;
+  m[11] = D12 + AmB;
+  m[12] = F(-2) * D12 + AmB;
+  m[13] = s[3] - s[4];
+  m[14] = s[7] - s[8];
+  m[15] = s[5] - s[6];
+  // odd rows, from the pair differences
+  const F X1 = d[3] - d[4], X2 = d[5] - d[6];
+  const F Y1 = d[3] + d[4], Y2 = d[7] - d[8];
+  const F Z1 = d[5] + d[6], Z2 = d[7] + d[8];
+  const F Xs = X1 + X2, Ys = Y1 + Y2, Zs = Z1 + Z2;
+  m[3] = d[0] + Xs;
+  m[4] = F(-4) * d[0] + Xs;
+  m[5] = d[1] + Ys;
+  m[6] = F(-4) * d[1] + Ys;
+  m[7] = d[2] + Zs;
+  m[8] = F(-4) * d[2] + Zs;
+  m[16] = X1 - X2;
+  m[17] = Y2 - Y1;
+  m[18] = Z1 - Z2;
+}
+
+// dg = T^T w for rows 1..18 (row 0, the conserved density, is not read), as the change of
+// g_0 and, for each pair (a, b), its even part e and odd part o: dg_a = e + o, dg_b = e - o.
+template <typename F>
+__host__ __device__ constexpr void back_transform(const F (&w)[Q], F& dg0, F (&e)[NP], F (&o)[NP]) {
+  // even rows
+  dg0 = F(-30) * w[1] + F(12) * w[2];
+  const F Eax = F(-11) * w[1] + F(-4) * w[2];
+  const F Edg = F(8) * w[1] + w[2];
+  const F U = F(2) * w[10] - w[9];
+  const F V = F(-2) * w[12] + w[11];
+  const F EU = Eax + U;
+  e[0] = F(-2) * U + Eax;
+  e[1] = EU + V;
+  e[2] = EU - V;
+  const F W9 = w[9] + w[10], W11 = w[11] + w[12];
+  const F EW = Edg + W9;
+  const F Exy = EW + W11, Exz = EW - W11, Eyz = F(-2) * W9 + Edg;
+  e[3] = Exy + w[13];
+  e[4] = Exy - w[13];
+  e[5] = Exz + w[15];
+  e[6] = Exz - w[15];
+  e[7] = Eyz + w[14];
+  e[8] = Eyz - w[14];
+  // odd rows
+  o[0] = F(-4) * w[4] + w[3];
+  o[1] = F(-4) * w[6] + w[5];
+  o[2] = F(-4) * w[8] + w[7];
+  const F Jx = w[3] + w[4], Jy = w[5] + w[6], Jz = w[7] + w[8];
+  o[3] = (Jx + Jy) + (w[16] - w[17]);
+  o[4] = (Jy - Jx) - (w[16] + w[17]);
+  o[5] = (Jx + Jz) + (w[18] - w[16]);
+  o[6] = (Jz - Jx) + (w[16] + w[18]);
+  o[7] = (Jy + Jz) + (w[17] - w[18]);
+  o[8] = (Jz - Jy) - (w[17] + w[18]);
+}
+
+// Both factored transforms reproduce T exactly on every unit vector.
+constexpr bool transforms_match_T() {
+  for (int i = 0; i < Q; ++i) {
+    long long g0 = i == 0, s[NP] = {}, d[NP] = {}, m[Q] = {};
+    for (int p = 0; p < NP; ++p) {
+      const long long ga = DV.pa[p] == i, gb = DV.pb[p] == i;
+      s[p] = ga + gb;
+      d[p] = ga - gb;
+    }
+    forward_transform<long long>(g0, s, d, m);
+    for (int k = 0; k < Q; ++k)
+      if (m[k] != TM[k][i]) return false;
+  }
+  for (int k = 1; k < Q; ++k) {
+    long long w[Q] = {}, dg0 = 0, e[NP] = {}, o[NP] = {};
+    w[k] = 1;
+    back_transform<long long>(w, dg0, e, o);
+    if (dg0 != TM[k][0]) return false;
+    for (int p = 0; p < NP; ++p)
+      if (e[p] + o[p] != TM[k][DV.pa[p]] || e[p] - o[p] != TM[k][DV.pb[p]]) return false;
+  }
+  return true;
+}
+static_assert(transforms_match_T(), "factored transforms must equal T and T^T");
+
+__device__ __forceinline__ void raw_moments(const Pairs& P, float (&m)[Q]) { forward_transform<float>(P.g0, P.s, P.d, m); }
+
+// m_k = sum_i T_ki g_i. Every caller evaluates the same factored expressions, so the
+// compiler shares them between the rows a kernel asks for.
 template <int K>
 __device__ __forceinline__ float moment(const Pairs& P) {
-  float acc = -0.0f;
-  if constexpr (DV.even[K]) {
-    acc = acc_int<TM[K][0]>(acc, P.g0);
-    static_for<NP>([&](auto pi) {
-      constexpr int p = pi;
-      acc = acc_int<TM[K][DV.pa[p]]>(acc, P.s[p]);
-    });
-  } else {
-    static_for<NP>([&](auto pi) {
-      constexpr int p = pi;
-      acc = acc_int<TM[K][DV.pa[p]]>(acc, P.d[p]);
-    });
-  }
-  return acc;
+  float m[Q];
+  raw_moments(P, m);
+  return m[K];
 }
 
-// j_a = sum_i c_ia g_i from the pair differences.
+// j_a = sum_i c_ia g_i (rows 3, 5, 7).
 template <int AX>
 __device__ __forceinline__ float momentum(const Pairs& P) {
-  float acc = -0.0f;
-  static_for<NP>([&](auto pi) {
-    constexpr int p = pi;
-    acc = acc_int<cax(AX, DV.pa[p])>(acc, P.d[p]);
-  });
-  return acc;
+  return moment<3 + 2 * AX>(P);
 }
 
-__device__ __forceinline__ float delta_rho(const Pairs& P) {
-  float acc = P.g0;
-  static_for<NP>([&](auto pi) { acc += P.s[decltype(pi)::value]; });
-  return acc;
-}
+__device__ __forceinline__ float delta_rho(const Pairs& P) { return moment<0>(P); }
 
 // Non-equilibrium moments m_k - m_k^eq for the non-conserved rows (Eq. meq, with rows 9..12
 // as in the equilibrium column of Eq. solvem). Index k of the returned array is row k;
@@ -309,31 +402,22 @@ __device__ __forceinline__ void force_moments(float jx, float jy, float jz, floa
   SF[18] = 0.f;
 }
 
-// g += T^-1 dm = T^T (D^-1 dm), using the pair parity. dm[k] for every row (0 if unused).
+// g += T^-1 dm = T^T (D^-1 dm) for rows 1..18 (dm[0] is not read: the density row is
+// conserved by every collision and every initial non-equilibrium part).
 __device__ __forceinline__ void add_back_transform(const float (&dm)[Q], float (&g)[Q]) {
   float w[Q];
+  w[0] = 0.0f;
   static_for<Q>([&](auto ki) {
     constexpr int k = ki;
-    w[k] = dm[k] * (1.0f / static_cast<float>(DV.D[k]));
+    if constexpr (k > 0) w[k] = dm[k] * (1.0f / static_cast<float>(DV.D[k]));
   });
-  float r0 = -0.0f;
-  static_for<Q>([&](auto ki) {
-    constexpr int k = ki;
-    if constexpr (DV.even[k]) r0 = acc_int<TM[k][0]>(r0, w[k]);
-  });
-  g[0] += r0;
+  float dg0, e[NP], o[NP];
+  back_transform<float>(w, dg0, e, o);
+  g[0] += dg0;
   static_for<NP>([&](auto pi) {
     constexpr int p = pi;
-    constexpr int a = DV.pa[p];
-    constexpr int b = DV.pb[p];
-    float e = -0.0f, o = -0.0f;
-    static_for<Q>([&](auto ki) {
-      constexpr int k = ki;
-      if constexpr (DV.even[k]) e = acc_int<TM[k][a]>(e, w[k]);
-      else o = acc_int<TM[k][a]>(o, w[k]);
-    });
-    g[a] += e + o;
-    g[b] += e - o;
+    g[DV.pa[p]] += e[p] + o[p];
+    g[DV.pb[p]] += e[p] - o[p];
   });
 }
 

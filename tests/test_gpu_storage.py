@@ -186,33 +186,45 @@ STEP_CASES = {
     "smag_yu": dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2),
     "implicit_chai_walls_force": dict(visc="smagorinsky_implicit", drive="chai", nu0=0.005, c_smag=0.3, walls=True,
                                       force=np.array([1e-5, 0.0, 0.0])),
+    "smag_chai_walls_corrected": dict(visc="smagorinsky", drive="chai", nu0=0.005, c_smag=0.3, walls=True,
+                                      force=np.array([2e-4, -1e-4, 5e-5]), corrected=True),
 }
 
+# every way a block pulls along x: whole rows with masked lanes (nx = 69), whole rows through
+# LDS (nx = 128 with two rows per block, 256), part rows (384)
+STEP_SHAPES = [(4, 10, 69), (3, 8, 128), (2, 5, 256), (2, 4, 384)]
 
+
+@pytest.mark.parametrize("shape", STEP_SHAPES)
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case", sorted(STEP_CASES))
-def test_storage_changes_only_the_rounding(storage, case):
+def test_storage_changes_only_the_rounding(storage, case, shape):
     """From a state representable in the storage format, a step with reduced storage gives
-    the FP32-stored step's result rounded to nearest even, bit for bit, and the same strain:
-    the arithmetic is the same FP32 arithmetic, only the stored values are rounded. Three
-    steps, the FP32 run restarted each time from the reduced run's state."""
+    the FP32-stored step's result rounded to nearest even, bit for bit, and the same strain
+    and adjoint record: the arithmetic is the same FP32 arithmetic, only the stored values
+    are rounded. Three steps, the FP32 run restarted each time from the reduced run's state."""
     import torch
     from oracle import storage as ost
     from paper_1704_07559_amd import capi, lbm
-    shape = (4, 10, 69)
+    kw = dict(STEP_CASES[case])
+    corrected = kw.pop("corrected", False)
     g0 = ost.round_storage(synth.random_state(19, shape, seed=11, scale=3e-3), storage)
-    _, c32, _ = spec_params(shape, **STEP_CASES[case])
-    _, cst, _ = spec_params(shape, storage=storage, **STEP_CASES[case])
+    _, c32, _ = spec_params(shape, **kw)
+    _, cst, _ = spec_params(shape, storage=storage, **kw)
+    c32.strain_force_correction = cst.strain_force_correction = int(corrected)
     a, b = lbm.LBM(c32), lbm.LBM(cst)
     b.set_populations(torch.as_tensor(g0).cuda())
     Sa, Sb = torch.empty((6,) + shape, device="cuda"), torch.empty((6,) + shape, device="cuda")
+    ra = torch.empty((1, a.save_planes) + shape, device="cuda")
+    rb = torch.empty_like(ra)
     for n in range(3):
         a.set_populations(b.populations())
         if a.s_nu is not None:
             a.s_nu.copy_(b.s_nu)
-        a.step(1, S_out=Sa, strain_kind=capi.LBM_STRAIN_CHAI)
-        b.step(1, S_out=Sb, strain_kind=capi.LBM_STRAIN_CHAI)
+        a.step(1, S_out=Sa, strain_kind=capi.LBM_STRAIN_CHAI, save=ra)
+        b.step(1, S_out=Sb, strain_kind=capi.LBM_STRAIN_CHAI, save=rb)
         assert torch.equal(Sa, Sb), n
+        assert torch.equal(ra, rb), n
         got = b.populations().cpu().numpy()
         ref = ost.round_storage(a.populations().cpu().numpy(), storage)
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (n, int((got != ref).sum()))
