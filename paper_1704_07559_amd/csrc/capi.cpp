@@ -119,7 +119,12 @@ void fill_model(lbm_ctx* c) {
   c->G.walls = p.walls_y;
   c->M.rho0 = static_cast<float>(p.rho0);
   c->M.inv_rho0 = static_cast<float>(1.0 / p.rho0);
-  for (int k = 0; k < 19; ++k) c->M.s[k] = static_cast<float>(k < c->Q ? p.s[k] : 0.0);
+  for (int k = 0; k < 19; ++k) {
+    c->M.s[k] = static_cast<float>(k < c->Q ? p.s[k] : 0.0);
+    const bool d3q19 = c->Q == 19;
+    c->M.sd[k] = d3q19 ? static_cast<float>(-p.s[k] / kD3Q19RowNorm[k]) : 0.0f;
+    c->M.fd[k] = d3q19 ? static_cast<float>((1.0 - 0.5 * p.s[k]) / kD3Q19RowNorm[k]) : 0.0f;
+  }
   c->M.om_eps = static_cast<float>(p.omega_eps);
   c->M.om_epsj = static_cast<float>(p.omega_epsj);
   c->M.om_xx = static_cast<float>(p.omega_xx);

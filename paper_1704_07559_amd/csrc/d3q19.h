@@ -121,6 +121,12 @@ constexpr Derived DV = derive();
 static_assert(DV.ok, "T must have orthogonal rows of definite parity");
 static_assert(DV.D[0] == 19 && DV.D[1] == 2394 && DV.D[2] == 252 && DV.D[9] == 36 && DV.D[10] == 72,
               "row norms of T");
+constexpr bool row_norms_match() {
+  for (int k = 0; k < Q; ++k)
+    if (DV.D[k] != kD3Q19RowNorm[k]) return false;
+  return true;
+}
+static_assert(row_norms_match(), "the host's row norms (relaxation constants) must be those of T");
 
 // ---------------------------------------------------------------------------------------
 // Per-node state in registers
@@ -402,15 +408,9 @@ __device__ __forceinline__ void force_moments(float jx, float jy, float jz, floa
   SF[18] = 0.f;
 }
 
-// g += T^-1 dm = T^T (D^-1 dm) for rows 1..18 (dm[0] is not read: the density row is
-// conserved by every collision and every initial non-equilibrium part).
-__device__ __forceinline__ void add_back_transform(const float (&dm)[Q], float (&g)[Q]) {
-  float w[Q];
-  w[0] = 0.0f;
-  static_for<Q>([&](auto ki) {
-    constexpr int k = ki;
-    if constexpr (k > 0) w[k] = dm[k] * (1.0f / static_cast<float>(DV.D[k]));
-  });
+// g += T^T w for rows 1..18 (w[0] is not read: the density row is conserved by every
+// collision and every initial non-equilibrium part).
+__device__ __forceinline__ void add_scaled_back_transform(const float (&w)[Q], float (&g)[Q]) {
   float dg0, e[NP], o[NP];
   back_transform<float>(w, dg0, e, o);
   g[0] += dg0;
@@ -419,6 +419,17 @@ __device__ __forceinline__ void add_back_transform(const float (&dm)[Q], float (
     g[DV.pa[p]] += e[p] + o[p];
     g[DV.pb[p]] += e[p] - o[p];
   });
+}
+
+// g += T^-1 dm = T^T (D^-1 dm) for rows 1..18 (dm[0] is not read).
+__device__ __forceinline__ void add_back_transform(const float (&dm)[Q], float (&g)[Q]) {
+  float w[Q];
+  w[0] = 0.0f;
+  static_for<Q>([&](auto ki) {
+    constexpr int k = ki;
+    if constexpr (k > 0) w[k] = dm[k] * (1.0f / static_cast<float>(DV.D[k]));
+  });
+  add_scaled_back_transform(w, g);
 }
 
 // Canonical populations from a non-equilibrium moment vector (rows given, others zero):

@@ -16,11 +16,17 @@ struct Geo {
   int walls;   // halfway bounce-back at y = -1/2 and y = ny - 1/2
 };
 
-// Model constants in FP32.
+// Row norms D_k = sum_i T_ki^2 of the D3Q19 transformation matrix (checked against T where
+// the device code derives them).
+constexpr int kD3Q19RowNorm[19] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+
+// Model constants in FP32. For D3Q19, sd and fd fold the row norms into the relaxation:
+// sd[k] = -s_k / D_k and fd[k] = (1 - s_k / 2) / D_k (zero for the other lattices).
 struct ModelF {
   float rho0, inv_rho0;
   float s[19];
   float om_eps, om_epsj, om_xx;
+  float sd[19], fd[19];
 };
 
 struct ViscF {
@@ -353,9 +359,16 @@ __device__ __forceinline__ void store_local(S* __restrict__ dst, const Geo& G, u
   });
 }
 
+// Square root and reciprocal as the single hardware instructions (within 1 ulp; the
+// correctly rounded library forms cost about ten instructions each, on every node). Their
+// arguments here are never subnormal where it matters: S:S >= 0 (a subnormal |S| changes
+// nu by nothing representable) and 3 nu + 1/2 >= 1/2.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // s_nu = 1 / (3 nu + 1/2) from the strain magnitude |S| = sqrt(2 S:S).
 __device__ __forceinline__ float viscous_rate(float SS, const ViscF& V) {
-  const float gamma = sqrtf(2.0f * SS);
+  const float gamma = fast_sqrt(2.0f * SS);
   float nu;
   if (V.kind == 1) {
     nu = V.nu0 + V.csmag2 * gamma;
@@ -364,7 +377,7 @@ __device__ __forceinline__ float viscous_rate(float SS, const ViscF& V) {
     else nu = (V.npl < 1.0f) ? V.numax : ((V.npl > 1.0f) ? V.numin : V.Kpl);
     nu = fminf(fmaxf(nu, V.numin), V.numax);
   }
-  return 1.0f / (3.0f * nu + 0.5f);
+  return fast_rcp(3.0f * nu + 0.5f);
 }
 
 // d nu / d gamma of the lagged models (zero where the power law is clamped or gamma = 0).
@@ -396,14 +409,14 @@ __device__ __forceinline__ float implicit_smagorinsky(const float (&P)[NC], cons
     PA += w * P[i] * A[i];
     AA += w * A[i] * A[i];
   }
-  const float q = k * sqrtf(2.0f * AA);
-  float s = 2.0f / (c + sqrtf(c * c + 4.0f * q));
+  const float q = k * fast_sqrt(2.0f * AA);
+  float s = 2.0f * fast_rcp(c + fast_sqrt(c * c + 4.0f * q));
 #pragma unroll
   for (int it = 0; it < 3; ++it) {
-    const float r = sqrtf(fmaxf(2.0f * (PP + s * (2.0f * PA + s * AA)), 0.0f));
-    const float dr = r > 0.0f ? 2.0f * (PA + s * AA) / r : 0.0f;
+    const float r = fast_sqrt(fmaxf(2.0f * (PP + s * (2.0f * PA + s * AA)), 0.0f));
+    const float dr = r > 0.0f ? 2.0f * (PA + s * AA) * fast_rcp(r) : 0.0f;
     const float f = s * (c + k * r) - 1.0f;
-    s -= f / (c + k * r + s * k * dr);
+    s -= f * fast_rcp(c + k * r + s * k * dr);
   }
   return s;
 }

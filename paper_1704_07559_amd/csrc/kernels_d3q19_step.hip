@@ -85,17 +85,21 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
     }
   }
 
-  // Relaxation in moment space: dm_k = -s_k (m_k - m_k^eq) + (1 - s_k/2) S_F,k.
-  float dm[Q];
-  dm[0] = 0.0f;
-  dm[3] = Fx;
-  dm[5] = Fy;
-  dm[7] = Fz;
+  // Relaxation in moment space, dm_k = -s_k (m_k - m_k^eq) + (1 - s_k/2) S_F,k, taken
+  // directly as w_k = dm_k / D_k for the back-transform g += T^T w: the row norms are folded
+  // into the rates (M.sd, M.fd; per node for the s_nu rows).
+  float w[Q];
+  w[0] = 0.0f;
+  constexpr float iD3 = 1.0f / static_cast<float>(DV.D[3]);
+  w[3] = Fx * iD3;
+  w[5] = Fy * iD3;
+  w[7] = Fz * iD3;
   static_for<Q>([&](auto ki) {
     constexpr int k = ki;
     if constexpr (k != 0 && k != 3 && k != 5 && k != 7) {
-      const float sk = is_nu_slot(k) ? snu : M.s[k];
-      dm[k] = -sk * n.m[k];
+      constexpr float iD = 1.0f / static_cast<float>(DV.D[k]);
+      const float c = is_nu_slot(k) ? -snu * iD : M.sd[k];
+      w[k] = c * n.m[k];
     }
   });
   if (Fo.mode) {
@@ -103,12 +107,13 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
     static_for<Q>([&](auto ki) {
       constexpr int k = ki;
       if constexpr (k != 0 && k != 3 && k != 5 && k != 7 && k < 16) {
-        const float sk = is_nu_slot(k) ? snu : M.s[k];
-        dm[k] = __builtin_fmaf(1.0f - 0.5f * sk, SF[k], dm[k]);
+        constexpr float iD = 1.0f / static_cast<float>(DV.D[k]);
+        const float c = is_nu_slot(k) ? __builtin_fmaf(-0.5f * iD, snu, iD) : M.fd[k];
+        w[k] = __builtin_fmaf(c, SF[k], w[k]);
       }
     });
   }
-  add_back_transform(dm, g);
+  add_scaled_back_transform(w, g);
 
   if (io.save) {
     // what the adjoint of this step needs: j, and for a strain-dependent viscosity the
