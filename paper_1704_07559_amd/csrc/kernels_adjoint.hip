@@ -52,24 +52,15 @@ struct LatFwd {
 
 // out_i = sum_k T_ki v_k (T^T v) with the pair parity of T.
 __device__ __forceinline__ void apply_transpose(const float (&v)[Q], float (&out)[Q]) {
-  float r0 = -0.0f;
-  static_for<Q>([&](auto ki) {
-    constexpr int k = ki;
-    if constexpr (DV.even[k]) r0 = acc_int<TM[k][0]>(r0, v[k]);
-  });
-  out[0] = r0;
+  // rows 1..18 by the factored back-transform, row 0 (all ones) added to every direction
+  float dg0, e[NP], o[NP];
+  back_transform<float>(v, dg0, e, o);
+  out[0] = dg0 + v[0];
   static_for<NP>([&](auto pi) {
     constexpr int p = pi;
-    constexpr int a = DV.pa[p];
-    constexpr int b = DV.pb[p];
-    float e = -0.0f, o = -0.0f;
-    static_for<Q>([&](auto ki) {
-      constexpr int k = ki;
-      if constexpr (DV.even[k]) e = acc_int<TM[k][a]>(e, v[k]);
-      else o = acc_int<TM[k][a]>(o, v[k]);
-    });
-    out[a] = e + o;
-    out[b] = e - o;
+    const float ep = e[p] + v[0];
+    out[DV.pa[p]] = ep + o[p];
+    out[DV.pb[p]] = ep - o[p];
   });
 }
 
