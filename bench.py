@@ -71,6 +71,36 @@ def read_traffic(name: str, sha: str):
         return None
 
 
+# VALU issue ceiling: one wave64 FP32 instruction takes 4 cycles on a SIMD (packed FP32 is
+# off), 256 CUs x 4 SIMDs at 2.4 GHz.
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def read_valu(label: str, sha: str):
+    """VALU instructions per launch of the step kernel from the committed rocprofv3 counter
+    summary (profiles/valu_step_d3q19_les.txt), if it was taken on the current kernel
+    source (else None)."""
+    f = ROOT / "profiles" / "valu_step_d3q19_les.txt"
+    if not f.exists():
+        return None
+    kv = {}
+    for line in f.read_text().splitlines():
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != sha:
+        return None
+    try:
+        return float(kv[f"{label}_valu_insts"])
+    except (KeyError, ValueError):
+        return None
+
+
+def valu_frac(insts, kernel_s):
+    """Fraction of the chip's VALU issue rate the kernel used (None without counts)."""
+    return None if insts is None else round(insts / kernel_s / VALU_WAVE_INSTS_PER_S, 4)
+
+
 def rates(tau_nu):
     # d'Humieres rates with s_nu = 1/tau_nu in slots 9, 11, 13, 14, 15
     sn = 1.0 / tau_nu
@@ -432,7 +462,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "lbm::d3q19::step_kernel<float, false, 2, false>",
                      "kernel_ms": round(kern * 1e3, 4), "bytes_per_node": bytes_per_node,
-                     "kernel_source_sha": sha},
+                     "kernel_source_sha": sha,
+                     "valu_issue_frac": valu_frac(read_valu("f32_les256", sha) if n == 256 else None, kern)},
         "diagnostics": {"mass": diag["mass"], "ke": diag["ke"], "umax": diag["umax"], "nonfinite": diag["nonfinite"]},
     }
     if win:
@@ -462,6 +493,8 @@ def main():
                                        "kernel_ms": round(k3 * 1e3, 4), "bytes_per_node": bpn,
                                        "hbm_frac": round(bpn * m ** 3 / k3 / 1e9 / HBM_PEAK_GBS, 4),
                                        "ke": d3["ke"], "nonfinite": d3["nonfinite"]}
+            if name == "f16":
+                extra[f"les384_{name}"]["valu_issue_frac"] = valu_frac(read_valu("f16_les384", sha), k3)
         # one rank's share of a z-slab decomposition of the 384^3 FP16 run over 8 GPUs: the
         # 384 x 384 x 48 interior, updated by the same kernel (its faces wrap periodically
         # here; a decomposed run would read them from 2 ghost planes exchanged per step)

@@ -1,4 +1,4 @@
-"""Host-side checks of bench.py (no GPU): the one-GPU contract, the traffic record lookup,
+"""Host-side checks of bench.py (no GPU): the one-GPU contract, the traffic and VALU record lookups,
 the relaxation-rate tables."""
 import os
 import subprocess
@@ -31,3 +31,15 @@ def test_rate_tables():
     assert {r19[k] for k in (9, 11, 13, 14, 15)} == {1.0 / (0.5 + 1.0 / 3.0)}
     assert {r15[k] for k in range(9, 14)} == {1.0 / 0.8}
     assert r19[0] == r19[3] == r19[5] == r19[7] == 0.0 and r15[0] == r15[3] == r15[5] == r15[7] == 0.0
+
+
+def test_valu_record_matches_only_its_kernel_source():
+    sha = bench.kernel_source_sha()
+    v = bench.read_valu("f16_les384", sha)
+    # one wave per 64 nodes, a few hundred VALU instructions per wave
+    assert v is None or 100 * 384**3 / 64 < v < 1000 * 384**3 / 64
+    assert bench.read_valu("f16_les384", "0" * 16) is None
+    assert bench.read_valu("no_such_run", sha) is None
+    assert bench.valu_frac(None, 1e-3) is None
+    # the issue ceiling: 614.4e9 wave instructions per second
+    assert abs(bench.valu_frac(614.4e6, 1e-3) - 1.0) < 1e-9
