@@ -272,8 +272,9 @@ def copy_bandwidth(torch, capi):
 def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50, visc="const"):
     """Strain-squared loss gradient on the 128^3 recipe (seeded spectrum velocity, uniform
     random force U(-1e-6, 1e-6), tau_nu = 0.8, 500 steps, checkpoint every 50): wall time of
-    the forward pass and of the backward pass (recompute + adjoint), and the adjoint kernel
-    alone against HBM. Algorithmic bytes per node of the adjoint kernel: 200 for a constant
+    the forward pass and of the backward pass (recompute + adjoint); the same with every
+    step's record kept by the forward sweep (no recompute; the gradient must come out with
+    the same bits); and the adjoint kernel alone against HBM. Algorithmic bytes per node of the adjoint kernel: 200 for a constant
     viscosity (76 lambda in, 76 out, 12 j, 12 F, 24 grad_F); with visc="smagorinsky" (lagged,
     C_s = 0.1 on top of nu0 = 0.1) 236 (+ 28 for the 7 extra record planes, + 8 for the
     s_nu-field adjoint in and out)."""
@@ -300,6 +301,20 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50
     J.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    gu_ck, gF_ck = u0.grad.clone(), F.grad.clone()
+    # the same gradient with every step's record kept by the forward sweep (no recompute;
+    # 12 or 40 bytes per node and step of HBM)
+    u0.grad, F.grad = None, None
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    Jr = ag.strain_loss(u0, F, ag.StrainLossProblem(p, nsteps, every, record_all=True))
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    Jr.backward()
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    same = bool(Jr.item() == J.item() and torch.equal(u0.grad, gu_ck) and torch.equal(F.grad, gF_ck))
+    torch.cuda.empty_cache()
     # adjoint kernel alone
     N = n ** 3
     p.force_field = F.detach().reshape(3, N)
@@ -321,8 +336,14 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50
     k_adj = e0.elapsed_time(e1) / 1e3 / reps
     sim.close()
     fwd, bwd = t1 - t0, t2 - t1
+    fwd_r, bwd_r = t4 - t3, t5 - t4
     return {"J": J.item(), "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
             "backward_over_forward": round(bwd / fwd, 3),
+            "recorded": {"forward_s": round(fwd_r, 4), "backward_s": round(bwd_r, 4),
+                         "backward_over_forward": round(bwd_r / fwd_r, 3),
+                         "gradient_over_plain_forward": round((fwd_r + bwd_r) / fwd, 3),
+                         "record_bytes": nsteps * (3 if visc == "const" else 10) * N * 4,
+                         "same_gradient_bits": same},
             "adjoint_kernel_ms": round(k_adj * 1e3, 4), "adjoint_bytes_per_node": bpn,
             "adjoint_hbm_frac": round(bpn * N / k_adj / 1e9 / HBM_PEAK_GBS, 4),
             "grad_u0_norm": float(u0.grad.norm()), "grad_F_norm": float(F.grad.norm())}

@@ -106,20 +106,25 @@ def test_strain_loss_gradient_16_cubed(nsteps, every):
     assert abs((F_t.grad.double() * dd).sum().item() - (gFr * d).sum()) < 1e-4 * abs((gFr * d).sum())
 
 
-def test_checkpoint_interval_does_not_change_the_gradient():
+@pytest.mark.parametrize("visc", ["const", "smagorinsky"])
+def test_checkpoint_interval_does_not_change_the_gradient(visc):
     """Recompute is bit-identical on the GPU too: the gradient with checkpoints every 7 steps
-    equals the gradient with one checkpoint."""
+    equals the gradient with one checkpoint, and both equal the gradient from records kept
+    by the forward sweep (no recompute), for a constant and a lagged viscosity."""
     import torch
     from paper_1704_07559_amd import autograd as ag
     shape, u0, F = _c4(12)
-    op, cp, _ = spec_params(shape, tau=0.8)
+    kw = {} if visc == "const" else dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.3)
+    op, cp, _ = spec_params(shape, tau=0.8, **kw)
     grads = []
-    for every in (21, 7):
+    for every, record_all in ((21, False), (7, False), (50, True)):
         u0_t = torch.as_tensor(u0.astype(np.float32)).cuda().requires_grad_(True)
         F_t = torch.as_tensor(F.astype(np.float32)).cuda().requires_grad_(True)
-        ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, 21, every)).backward()
-        grads.append((u0_t.grad.clone(), F_t.grad.clone()))
-    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+        J = ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, 21, every, record_all=record_all))
+        J.backward()
+        grads.append((J.item(), u0_t.grad.clone(), F_t.grad.clone()))
+    for g in grads[1:]:
+        assert g[0] == grads[0][0] and torch.equal(g[1], grads[0][1]) and torch.equal(g[2], grads[0][2])
 
 
 def test_strain_loss_gradient_500_steps_against_stored_oracle():
