@@ -106,11 +106,12 @@ def test_strain_loss_gradient_16_cubed(nsteps, every):
     assert abs((F_t.grad.double() * dd).sum().item() - (gFr * d).sum()) < 1e-4 * abs((gFr * d).sum())
 
 
-@pytest.mark.parametrize("visc", ["const", "smagorinsky"])
-def test_checkpoint_interval_does_not_change_the_gradient(visc):
+@pytest.mark.parametrize("visc,nsteps", [("const", 21), ("smagorinsky", 21), ("const", 0)])
+def test_checkpoint_interval_does_not_change_the_gradient(visc, nsteps):
     """Recompute is bit-identical on the GPU too: the gradient with checkpoints every 7 steps
     equals the gradient with one checkpoint, and both equal the gradient from records kept
-    by the forward sweep (no recompute), for a constant and a lagged viscosity."""
+    by the forward sweep (no recompute), for a constant and a lagged viscosity, and for a
+    run of no steps (the loss of the initial state)."""
     import torch
     from paper_1704_07559_amd import autograd as ag
     shape, u0, F = _c4(12)
@@ -120,7 +121,7 @@ def test_checkpoint_interval_does_not_change_the_gradient(visc):
     for every, record_all in ((21, False), (7, False), (50, True)):
         u0_t = torch.as_tensor(u0.astype(np.float32)).cuda().requires_grad_(True)
         F_t = torch.as_tensor(F.astype(np.float32)).cuda().requires_grad_(True)
-        J = ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, 21, every, record_all=record_all))
+        J = ag.strain_loss(u0_t, F_t, ag.StrainLossProblem(cp, nsteps, every, record_all=record_all))
         J.backward()
         grads.append((J.item(), u0_t.grad.clone(), F_t.grad.clone()))
     for g in grads[1:]:
