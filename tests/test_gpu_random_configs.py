@@ -1,0 +1,92 @@
+"""Seeded random configurations of the step on every lattice against the FP64 oracles: box
+shapes whose row length picks every launch shape (whole rows with masked lanes, whole rows
+through LDS with one to four rows per block, part rows, one node), every viscosity kind and
+drive, walls, no / uniform / field forcing, the force-corrected strain, and tau (D3Q19 also
+rho0). Three steps from a far-from-equilibrium state each; populations 1e-5 and both strain
+formulas 1e-4, as for the fixed cases."""
+import numpy as np
+import pytest
+
+import synth
+from tests._common import needs_gpu, pop_rel_err, spec_params, strain_rel_err, to_np
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+NX = [1, 2, 3, 17, 63, 64, 65, 128, 130, 192, 255, 256, 257, 320, 384, 448]
+VISC = ["const", "smagorinsky", "powerlaw", "smagorinsky_implicit"]
+NCONF = {"d3q19": 24, "d3q15": 12, "d2q9": 12}
+CASES = [(lat, k) for lat, n in NCONF.items() for k in range(n)]
+
+
+def _config(lat, k):
+    rng = np.random.default_rng({"d3q19": 1704, "d3q15": 7559, "d2q9": 2017}[lat] + k)
+    nx = int(NX[k % len(NX)])
+    ny = int(rng.integers(1, 13))
+    nz = 1 if lat == "d2q9" else int(rng.integers(1, 5))
+    while nx * ny * nz > 24000:
+        ny = max(1, ny // 2)
+        nz = max(1, nz // 2)
+    walls = bool(rng.integers(0, 2)) and ny >= 2
+    visc = VISC[int(rng.integers(0, len(VISC)))]
+    tau = float(rng.uniform(0.55, 1.2))
+    kw = dict(tau=tau, walls=walls, visc=visc, drive=["yu", "chai"][int(rng.integers(0, 2))])
+    rho0 = float(rng.choice([1.0, 1.5]))
+    if lat == "d3q19":
+        kw["rho0"] = rho0
+    if visc in ("smagorinsky", "smagorinsky_implicit"):
+        kw.update(nu0=(tau - 0.5) / 3.0, c_smag=float(rng.uniform(0.05, 0.5)))
+    elif visc == "powerlaw":
+        kw.update(K_pl=float(rng.uniform(0.01, 0.3)), n_pl=float(rng.choice([0.5, 0.8, 1.3])), nu_min=1e-3,
+                  nu_max=1.0)
+    force = ["none", "uniform", "field"][int(rng.integers(0, 3))]
+    corrected = force != "none" and bool(rng.integers(0, 2))
+    return (nz, ny, nx), kw, force, corrected
+
+
+def _setup(lat, k):
+    shape, kw, force, corrected = _config(lat, k)
+    print(f"{lat} config {k}: shape {shape} {kw} force={force} corrected={corrected}", flush=True)
+    dim = 2 if lat == "d2q9" else 3
+    if force == "uniform":
+        kw["force"] = np.array([2e-5, -1e-5, 5e-6][:dim])
+    elif force == "field":
+        kw["force"] = synth.uniform_random_force(shape, seed=100 + k, amp=1e-4)[:dim]
+    if lat == "d3q19":
+        from oracle import d3q19 as od
+        op, cp, _ = spec_params(shape, **kw)
+        q, ncomp, rho0 = 19, 6, kw["rho0"]
+    elif lat == "d3q15":
+        from oracle import d3q15 as od
+        from tests.test_gpu_d3q15 import _spec
+        op, cp = _spec(shape, **kw)
+        q, ncomp, rho0 = 15, 6, 1.0
+    else:
+        from oracle import d2q9 as od
+        from tests.test_gpu_d2q9 import _spec
+        op, cp = _spec(shape, **kw)
+        q, ncomp, rho0 = 9, 3, 1.0
+    if corrected:
+        op.force_corrected = True
+        cp.strain_force_correction = 1
+    return shape, od, op, cp, q, ncomp, rho0
+
+
+@pytest.mark.parametrize("lat,k", CASES)
+def test_random_configuration(lat, k):
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape, od, op, cp, q, ncomp, rho0 = _setup(lat, k)
+    sim = lbm.LBM(cp)
+    g0 = synth.random_state(q, shape, seed=200 + k, scale=3e-3).astype(np.float32).astype(np.float64)
+    sim.set_populations(torch.as_tensor(g0.astype(np.float32)).cuda())
+    ref = od.Simulation(op, g0)
+    S = torch.empty((ncomp,) + shape, device="cuda")
+    for n in range(3):
+        S_chai = to_np(sim.strain(capi.LBM_STRAIN_CHAI))
+        sim.step(1, S_out=S, strain_kind=capi.LBM_STRAIN_YU)
+        out = ref.step(1)
+        Sy, Sc = (out.S_yu, out.S_chai) if lat == "d3q19" else out
+        assert strain_rel_err(to_np(S), Sy) < 1e-4, n
+        assert strain_rel_err(S_chai, Sc) < 1e-4, n
+        assert pop_rel_err(to_np(sim.populations()), ref.g, rho0, od.W) < 1e-5, n
+    sim.close()
