@@ -3,7 +3,8 @@ shapes whose row length picks every launch shape (whole rows with masked lanes, 
 through LDS with one to four rows per block, part rows, one node), every viscosity kind and
 drive, walls, no / uniform / field forcing, the force-corrected strain, and tau (D3Q19 also
 rho0). Three steps from a far-from-equilibrium state each; populations 1e-5 and both strain
-formulas 1e-4, as for the fixed cases."""
+formulas 1e-4, as for the fixed cases; and, with 16-bit storage, the bit-exact rounding property
+of the storage tests."""
 import numpy as np
 import pytest
 
@@ -90,3 +91,38 @@ def test_random_configuration(lat, k):
         assert strain_rel_err(S_chai, Sc) < 1e-4, n
         assert pop_rel_err(to_np(sim.populations()), ref.g, rho0, od.W) < 1e-5, n
     sim.close()
+
+
+ROUNDING_CASES = [(lat, k) for lat in NCONF for k in range(8)]
+
+
+@pytest.mark.parametrize("lat,k", ROUNDING_CASES)
+def test_random_configuration_storage_changes_only_the_rounding(lat, k):
+    """The same random configurations with FP16 (even k) or BF16 (odd k) storage: from a
+    state representable in the format, each of three steps equals the FP32-stored step
+    rounded to nearest even, bit for bit, with the same strain and s_nu."""
+    import torch
+    from oracle import storage as ost
+    from paper_1704_07559_amd import capi, lbm
+    storage = "f16" if k % 2 == 0 else "bf16"
+    shape, od, op, c32, q, ncomp, rho0 = _setup(lat, k)
+    _, _, _, cst, _, _, _ = _setup(lat, k)
+    cst.storage = {"f16": capi.LBM_F16, "bf16": capi.LBM_BF16}[storage]
+    a, b = lbm.LBM(c32), lbm.LBM(cst)
+    g0 = ost.round_storage(synth.random_state(q, shape, seed=300 + k, scale=3e-3), storage)
+    b.set_populations(torch.as_tensor(g0).cuda())
+    Sa, Sb = torch.empty((ncomp,) + shape, device="cuda"), torch.empty((ncomp,) + shape, device="cuda")
+    for n in range(3):
+        a.set_populations(b.populations())
+        if a.s_nu is not None:
+            a.s_nu.copy_(b.s_nu)
+        a.step(1, S_out=Sa, strain_kind=capi.LBM_STRAIN_CHAI)
+        b.step(1, S_out=Sb, strain_kind=capi.LBM_STRAIN_CHAI)
+        assert torch.equal(Sa, Sb), n
+        got = b.populations().cpu().numpy()
+        ref = ost.round_storage(a.populations().cpu().numpy(), storage)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (n, int((got != ref).sum()))
+        if a.s_nu is not None:
+            assert torch.equal(a.s_nu, b.s_nu), n
+    a.close()
+    b.close()
