@@ -3,8 +3,8 @@ shapes whose row length picks every launch shape (whole rows with masked lanes, 
 through LDS with one to four rows per block, part rows, one node), every viscosity kind and
 drive, walls, no / uniform / field forcing, the force-corrected strain, and tau (D3Q19 also
 rho0). Three steps from a far-from-equilibrium state each; populations 1e-5 and both strain
-formulas 1e-4, as for the fixed cases; and, with 16-bit storage, the bit-exact rounding property
-of the storage tests."""
+formulas 1e-4, as for the fixed cases; with 16-bit storage, the bit-exact rounding property
+of the storage tests; and one D3Q19 adjoint step per configuration against the oracle's."""
 import numpy as np
 import pytest
 
@@ -126,3 +126,59 @@ def test_random_configuration_storage_changes_only_the_rounding(lat, k):
             assert torch.equal(a.s_nu, b.s_nu), n
     a.close()
     b.close()
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a, dtype=np.float64) - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("k", range(NCONF["d3q19"]))
+def test_random_configuration_adjoint_step(k):
+    """One D3Q19 adjoint step (lbm_adjoint_step) in every D3Q19 configuration above,
+    against the oracle's adjoint: dJ/dg, dJ/dF and, for the lagged viscosities, the adjoint
+    of the s_nu field; 1e-5 of the largest value, as for the fixed cases."""
+    import torch
+    from oracle import adjoint as adj
+    from oracle import adjoint_visc as av
+    from oracle import d3q19 as od
+    from paper_1704_07559_amd import capi, lbm
+    shape, _, op, cp, _, _, _ = _setup("d3q19", k)
+    N = cp.N
+    F = op.force
+    if F is None:
+        F = np.zeros((3,) + shape)
+    elif np.asarray(F).shape == (3,):
+        F = np.broadcast_to(np.asarray(F, dtype=np.float64).reshape(3, 1, 1, 1), (3,) + shape).copy()
+    F = np.asarray(F, dtype=np.float32).astype(np.float64)
+    u = synth.random_vector(shape, seed=400 + k, scale=0.05)
+    g = od.init_populations(np.zeros(shape), u, op) + synth.random_state(19, shape, seed=500 + k, scale=3e-3)
+    g = g.astype(np.float32).astype(np.float64)
+    sim = lbm.LBM(cp)
+    sim.set_populations(torch.as_tensor(g.astype(np.float32)).cuda())
+    sp = None
+    if op.visc_kind in ("smagorinsky", "powerlaw"):
+        sp = 1.0 / (3.0 * (0.02 + 0.01 * synth.random_state(1, shape, seed=600 + k, scale=1.0)[0] ** 2) + 0.5)
+        sp = sp.astype(np.float32).astype(np.float64)
+        sim.s_nu.copy_(torch.as_tensor(sp.reshape(-1).astype(np.float32)))
+    A = sim.adjoint_planes
+    rec = torch.empty((1, sim.save_planes, N), device="cuda")
+    sim.step(1, save=rec)
+    lam_in = synth.random_state(A, shape, seed=700 + k, scale=1.0).astype(np.float32).astype(np.float64)
+    lam_t = torch.as_tensor(lam_in.astype(np.float32)).cuda().reshape(A, N).contiguous()
+    lam_out = torch.empty_like(lam_t)
+    gF = torch.zeros((3, N), device="cuda")
+    capi.lbm_adjoint_step(sim.ctx, rec[0], lam_t, lam_out, gF)
+    pf = adj._with_force(op, F)
+    out = to_np(lam_out).reshape((A,) + shape)
+    if op.visc_kind == "const":
+        ref_lam, ref_gF = adj.adjoint_step(lam_in, g, F, pf)
+        ref_lams = None
+    else:
+        ref_lam, ref_lams, ref_gF = av.adjoint_step_visc(lam_in[:19], lam_in[19] if sp is not None else None, g, sp,
+                                                         F, pf)
+    assert _rel(out[:19], ref_lam) < 1e-5
+    if np.abs(ref_gF).max() > 0:
+        assert _rel(to_np(gF).reshape(ref_gF.shape), ref_gF) < 1e-5
+    if sp is not None:
+        assert _rel(out[19], ref_lams) < 1e-5
+    sim.close()
