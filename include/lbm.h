@@ -160,6 +160,11 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
  *               strain_force_correction), and plane 9, the
  *               s_nu its strain was taken with (the lagged field value, or the implicitly
  *               solved rate).
+ * Only kernel launches are queued on `stream` (no allocation, copy or wait), so calls can be
+ * captured into a HIP graph. The context alternates its two population buffers on the host
+ * at every step: a captured sequence must hold an even number of steps for each replay to
+ * start from the buffer the capture started from, and lbm_step_count counts the captured
+ * steps only.
  */
 lbm_status lbm_step(lbm_ctx* ctx, int nsteps, float* S_out, int strain_kind, float* save, void* stream);
 
