@@ -22,20 +22,25 @@ BOXES = {
     "d3q19_f32": (19, "f32", (2, 7612, 7424)),
     "d3q19_f16": (19, "f16", (1, 11037, 10240)),
     "d3q15_f32": (15, "f32", (2, 8473, 8448)),
+    "d3q15_f16": (15, "f16", (2, 13981, 10240)),
     "d2q9_f32": (9, "f32", (1, 10965, 10880)),
+    "d2q9_f16": (9, "f16", (1, 14563, 16384)),
 }
 
 
 def _spec(q, shape, storage):
+    from paper_1704_07559_amd import capi
     from tests._common import spec_params
     if q == 19:
         op, cp, _ = spec_params(shape, tau=0.51, storage=storage, **LES)
         return op, cp
     if q == 15:
-        from tests.test_gpu_d3q15 import _spec as spec15
-        return spec15(shape, tau=0.51, **LES)
-    from tests.test_gpu_d2q9 import _spec as spec9
-    return spec9(shape, tau=0.51, **LES)
+        from tests.test_gpu_d3q15 import _spec as spec_other
+    else:
+        from tests.test_gpu_d2q9 import _spec as spec_other
+    op, cp = spec_other(shape, tau=0.51, **LES)
+    cp.storage = {"f32": capi.LBM_F32, "f16": capi.LBM_F16, "bf16": capi.LBM_BF16}[storage]
+    return op, cp
 
 
 @pytest.mark.parametrize("box", sorted(BOXES))
