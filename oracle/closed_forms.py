@@ -79,3 +79,35 @@ def startup_poiseuille(eta: np.ndarray, H: float, F: float, nu: float, t: float,
         u = u - 4.0 * F * H * H / (nu * kk**3 * np.pi**3) * np.sin(kk * np.pi * eta / H) * \
             np.exp(-nu * kk * kk * np.pi * np.pi * t / (H * H))
     return u
+
+
+def smagorinsky_poiseuille(eta: np.ndarray, H: float, F: float, nu0: float, c_smag: float,
+                           rho0: float = 1.0) -> np.ndarray:
+    """Steady plane channel flow between walls at eta = 0 and H under a uniform body force F
+    along the walls, with the Smagorinsky viscosity nu = nu0 + C_s^2 |S|, |S| = sqrt(2 S:S).
+
+    For a velocity u(eta) along the walls the strain has one independent component,
+    S_{eta u} = u'/2, so 2 S:S = 4 (u'/2)^2 = u'^2 and |S| = |u'|. The stress balance at
+    distance s = |eta - H/2| from the mid-plane, rho0 (nu0 + C_s^2 |u'|) |u'| = F s, is a
+    quadratic in |u'| with the positive root
+      |u'|(s) = (q(s) - nu0) / (2 C_s^2),   q(s) = sqrt(nu0^2 + 4 C_s^2 F s / rho0).
+    With u = 0 at the wall (s = H/2) and the substitution s = (q^2 - nu0^2) rho0 / (4 C_s^2 F),
+      u = int_s^{H/2} |u'| ds'
+        = (H/2 - s) / (2 (q_w + q)) [ nu0 (e_w + e) + (2/3) C_s^2 (e_w^2 + e_w e + e^2) ],
+    where q_w = q(H/2) and e(s) = (q(s) - nu0) / C_s^2 = 4 F s / (rho0 (q(s) + nu0)); this
+    form has no cancellation as C_s -> 0, where it tends to the Newtonian profile
+    F ((H/2)^2 - s^2) / (2 rho0 nu0).
+    """
+    c2 = c_smag * c_smag
+    half = H / 2.0
+    s = np.abs(np.asarray(eta, dtype=np.float64) - half)
+
+    def q(dist):
+        return np.sqrt(nu0 * nu0 + 4.0 * c2 * F * dist / rho0)
+
+    def e(dist, qd):
+        return 4.0 * F * dist / (rho0 * (qd + nu0))
+
+    qw, qs = q(half), q(s)
+    ew, es = e(half, qw), e(s, qs)
+    return (half - s) / (2.0 * (qw + qs)) * (nu0 * (ew + es) + (2.0 / 3.0) * c2 * (ew * ew + ew * es + es * es))
