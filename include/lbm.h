@@ -247,6 +247,26 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, int nsteps, const float* rec, float* 
                              float* grad_force, void* stream);
 
 /*
+ * lbm_adjoint_steps without the lam_b workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc). The
+ * reverse sweep ping-pongs between `lam` (device float[lbm_adjoint_planes(ctx)*N]: on entry
+ * the adjoint after the last step, on return the adjoint before the first) and a fixed
+ * scratch of 64 MiB that the library holds on every device it runs on (a static device
+ * array, not allocated by this call), so A*N*4 bytes must not exceed 64 MiB (A =
+ * lbm_adjoint_planes: about 838 000 nodes with 20 planes). rec and grad_force as in
+ * lbm_adjoint_steps; the result equals lbm_adjoint_steps' bit for bit. The call allocates
+ * nothing: it validates, looks up the scratch address of the stream's device (once per
+ * device), and queues the kernel launches and, for an odd nsteps, one device-to-device copy
+ * into lam. Every call on one device shares that device's scratch, which keeps the last
+ * call's contents (every step overwrites it whole, so nothing needs clearing): calls that
+ * overlap on one device (several streams, several host threads) race and must be ordered by
+ * the caller. Errors: LBM_EINVAL (NULL or misaligned pointers, nsteps < 0, the state larger
+ * than the scratch), LBM_EUNSUPPORTED (D2Q9, D3Q15), LBM_EHIP.
+ */
+lbm_status lbm_adjoint_steps_noalloc(lbm_ctx* ctx, int nsteps, const float* rec, float* lam, float* grad_force,
+                                     void* stream);
+
+/*
  * Loss J = sum_x S:S of the current pre-collision state (Yu formula, which equals Chai,
  * Section 5.1, at the rate the viscosity model gives the state: s_nu of the parameters, the
  * lagged field, or the implicitly solved rate), its gradient into lam_out (device

@@ -32,7 +32,7 @@ LBM_VISC_CONST, LBM_VISC_SMAGORINSKY, LBM_VISC_POWERLAW, LBM_VISC_SMAGORINSKY_IM
 EXPORTED = (
     "lbm_params_size", "lbm_population_bytes", "lbm_init", "lbm_step", "lbm_strain", "lbm_reduce", "lbm_get_populations",
     "lbm_set_populations", "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_step_count",
-    "lbm_set_step_count", "lbm_save_planes", "lbm_adjoint_planes", "lbm_adjoint_step", "lbm_adjoint_steps", "lbm_strain_loss_seed", "lbm_init_adjoint", "lbm_destroy",
+    "lbm_set_step_count", "lbm_save_planes", "lbm_adjoint_planes", "lbm_adjoint_step", "lbm_adjoint_steps", "lbm_adjoint_steps_noalloc", "lbm_strain_loss_seed", "lbm_init_adjoint", "lbm_destroy",
     "lbm_status_string", "lbm_last_error", "lbm_stream_copy", "lbm_reduce_async",
 )
 
@@ -75,6 +75,7 @@ _sig = {
     "lbm_adjoint_planes": (ctypes.c_int, [_ctx_p]),
     "lbm_adjoint_step": (ctypes.c_int, [_ctx_p, _vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_steps": (ctypes.c_int, [_ctx_p, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "lbm_adjoint_steps_noalloc": (ctypes.c_int, [_ctx_p, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "lbm_strain_loss_seed": (ctypes.c_int, [_ctx_p, _vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "lbm_init_adjoint": (ctypes.c_int, [_ctx_p, _vp, _vp, _vp, _vp]),
     "lbm_destroy": (None, [_ctx_p]),
@@ -260,6 +261,11 @@ def lbm_adjoint_step(ctx: int, rec_n, lam_in, lam_out, grad_force=None, stream=N
 def lbm_adjoint_steps(ctx: int, nsteps: int, rec, lam_a, lam_b, grad_force=None, stream=None):
     _check(_lib.lbm_adjoint_steps(ctx, int(nsteps), _ptr(rec), _ptr(lam_a), _ptr(lam_b), _ptr(grad_force),
                                   _stream(stream)), "lbm_adjoint_steps")
+
+
+def lbm_adjoint_steps_noalloc(ctx: int, nsteps: int, rec, lam, grad_force=None, stream=None):
+    _check(_lib.lbm_adjoint_steps_noalloc(ctx, int(nsteps), _ptr(rec), _ptr(lam), _ptr(grad_force), _stream(stream)),
+           "lbm_adjoint_steps_noalloc")
 
 
 def lbm_strain_loss_seed(ctx: int, lam_out, grad_force=None, stream=None) -> float:

@@ -462,6 +462,43 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int nsteps, const float* rec, float* la
   return LBM_OK;
 }
 
+lbm_status lbm_adjoint_steps_noalloc(lbm_ctx* c, int nsteps, const float* rec, float* lam, float* grad_force,
+                                     void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint is provided for D3Q19");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  if ((st = check_field(rec, "rec")) != LBM_OK) return st;
+  if ((st = check_field(lam, "lam")) != LBM_OK) return st;
+  if (grad_force && !aligned(grad_force, 4)) return fail(LBM_EINVAL, "grad_force must be 4-byte aligned");
+  const size_t lam_bytes = sizeof(float) * adjoint_planes(c) * static_cast<size_t>(c->G.N);
+  if (lam_bytes > kNoAllocScratchBytes)
+    return fail(LBM_EINVAL, "lbm_adjoint_steps_noalloc: the adjoint state (" + std::to_string(lam_bytes) +
+                                " bytes) exceeds the fixed scratch of " + std::to_string(kNoAllocScratchBytes) +
+                                " bytes; use lbm_adjoint_steps with a caller-owned lam_b");
+  if (nsteps == 0) return LBM_OK;
+  const hipStream_t s = as_stream(stream);
+  void* scratch = nullptr;
+  hipError_t e = noalloc_scratch(s, &scratch);
+  if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps_noalloc scratch lookup");
+  const size_t rec_elems = static_cast<size_t>(save_planes(c->V)) * c->G.N;
+  float* in = lam;
+  float* out = static_cast<float*>(scratch);
+  for (int n = nsteps - 1; n >= 0; --n) {
+    e = d3q19::launch_adjoint_step(c->G, c->M, c->V, c->F, rec + static_cast<size_t>(n) * rec_elems, in, out,
+                                   grad_force, s);
+    if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps_noalloc");
+    float* t = in;
+    in = out;
+    out = t;
+  }
+  if (in != lam) {
+    e = hipMemcpyAsync(lam, in, lam_bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps_noalloc copy");
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_strain_loss_seed(lbm_ctx* c, float* lam_out, float* grad_force, double* J_host, void* stream) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;

@@ -58,6 +58,14 @@ hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, c
                          const float* snu, double* partials, double* out, hipStream_t);
 }  // namespace d3q15
 
+// Fixed device scratch of the allocation-free adjoint sweep: room for one adjoint state of up
+// to 64 MiB (A planes of N floats), held by every device the library runs on.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+
+// Address of that scratch on the device of `stream` (looked up on the first call per device;
+// no allocation).
+hipError_t noalloc_scratch(hipStream_t stream, void** out);
+
 hipError_t launch_reduce_final(const double* partials, int nblocks, double* out, hipStream_t);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t);
 

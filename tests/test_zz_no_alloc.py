@@ -1,0 +1,79 @@
+"""lbm_adjoint_steps_noalloc (the adjoint sweep without a caller-owned workspace, for callers
+that cannot allocate device memory) against lbm_adjoint_steps with its lam_b workspace.
+
+Both run the same kernels on the same records, so the adjoint state and the accumulated
+force gradient must agree bit for bit. Two calls in a row on one device, the second on a
+smaller box, check that the shared scratch carries nothing from one call into the next; the
+first (lagged Smagorinsky with walls and a force field: 20 planes, an odd step count, so the
+result comes back by the final copy) and the second (constant viscosity, uniform force:
+19 planes, an even step count) cover both plane counts and both ways the sweep ends.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests._common import needs_gpu, spec_params
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def _forward_records(shape, nsteps, seed, **spec):
+    import torch
+    from oracle import d3q19 as od
+    from paper_1704_07559_amd import lbm
+    op, cp, ft = spec_params(shape, **spec)
+    sim = lbm.LBM(cp)
+    u = synth.random_vector(shape, seed=seed, scale=0.03)
+    g = od.init_populations(np.zeros(shape), u, op) + synth.random_state(19, shape, seed=seed + 1, scale=2e-3)
+    sim.set_populations(torch.as_tensor(g.astype(np.float32)).cuda())
+    rec = torch.empty((nsteps, sim.save_planes, cp.N), device="cuda")
+    sim.step(nsteps, save=rec)
+    return sim, rec, ft
+
+
+def _compare(shape, nsteps, seed, **spec):
+    import torch
+    from paper_1704_07559_amd import capi
+    sim, rec, _ = _forward_records(shape, nsteps, seed, **spec)
+    N, A = sim.params.N, sim.adjoint_planes
+    lam0 = torch.as_tensor(synth.random_state(A, shape, seed=seed + 2, scale=1.0).astype(np.float32)).cuda()
+    lam0 = lam0.reshape(A, N).contiguous()
+    gF0 = torch.as_tensor(synth.random_state(3, shape, seed=seed + 3, scale=1e-3).astype(np.float32)).cuda()
+    gF0 = gF0.reshape(3, N).contiguous()
+    # the existing entry point with its workspace
+    lam_a, lam_b, gF_ref = lam0.clone(), torch.empty_like(lam0), gF0.clone()
+    capi.lbm_adjoint_steps(sim.ctx, nsteps, rec, lam_a, lam_b, gF_ref)
+    # the allocation-free variant
+    lam, gF = lam0.clone(), gF0.clone()
+    capi.lbm_adjoint_steps_noalloc(sim.ctx, nsteps, rec, lam, gF)
+    torch.cuda.synchronize()
+    assert torch.equal(lam, lam_a), float((lam - lam_a).abs().max())
+    assert torch.equal(gF, gF_ref), float((gF - gF_ref).abs().max())
+    assert not torch.equal(lam, lam0)  # the sweep did something
+    sim.close()
+
+
+def test_noalloc_adjoint_sweep_matches_workspace_version_twice():
+    shape1 = (6, 10, 70)
+    F1 = synth.uniform_random_force(shape1, seed=11, amp=1e-4)
+    _compare(shape1, 5, 20, tau=0.7, walls=True, force=F1, visc="smagorinsky", nu0=0.02, c_smag=0.3)
+    # second call on the same device, smaller box, whole-row LDS blocks (nx = 64)
+    _compare((3, 8, 64), 4, 40, tau=0.75, force=(1e-5, -2e-5, 3e-5))
+
+
+def test_noalloc_rejects_states_beyond_the_scratch():
+    """An adjoint state larger than the fixed scratch (19 planes x 2^20 nodes = 80 MB > 64 MiB)
+    is refused with LBM_EINVAL before anything is queued (nsteps = 0 here, so a missing check
+    could not launch anything either)."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape = (64, 128, 128)
+    _, cp, _ = spec_params(shape, tau=0.8)
+    sim = lbm.LBM(cp)
+    rec = torch.empty((1, sim.save_planes, cp.N), device="cuda")
+    lam = torch.empty((sim.adjoint_planes, cp.N), device="cuda")
+    with pytest.raises(capi.LBMError) as ei:
+        capi.lbm_adjoint_steps_noalloc(sim.ctx, 0, rec, lam, None)
+    assert ei.value.status == capi.LBM_EINVAL
+    assert "exceeds the fixed scratch" in str(ei.value)
+    sim.close()
