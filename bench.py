@@ -7,15 +7,22 @@ node, initial velocity a seeded random solenoidal field with spectrum k^4 exp(-2
 and u_rms = 0.04 (seed 1704). One step = one launch of the fused kernel (pull streaming,
 moments, equilibrium, Yu strain, Smagorinsky s_nu, relaxation, back-transform, store) over
 all 16.8 M nodes; the FP64 diagnostics reduction (mass, momentum, energy, strain, max |u|,
-non-finite watchdog) runs every 100 steps inside the timed region.
+non-finite watchdog) runs after every 100 steps, inside the timed region (a run of fewer steps
+has none inside and is checked once after the timing).
 
 Output: one JSON line. ``value`` is MLUPS (million lattice-node updates per second) with
-inputs resident in HBM. ``roofline`` prices the step kernel's algorithmic bytes per node
+inputs resident in HBM, over exactly --steps timed steps after --warmup untimed ones (the
+device is first kept busy for a quarter second with STREAM-style copies, so the run does not
+start from an idle GPU). ``roofline`` prices the step kernel's algorithmic bytes per node
 (19 reads + 19 writes of 4 B, plus the 4 B read and write of the lagged s_nu field) against
-the 8 TB/s HBM peak, timed with HIP events around every 10th launch of the timed region on
-the stream it runs on (events on every launch would add their own gaps to the run).
-``extra`` carries the FP16/BF16-stored 384^3 runs and their FP32 reference.
-``cpu_baseline`` times the FP64 oracle on a bounded slab of the same workload.
+the 8 TB/s HBM peak; its kernel time is the device time of all timed launches (HIP events
+on the launch stream around every run of launches between two diagnostics), divided by the
+number of launches. ``extra`` carries the other workloads (FP16/BF16-stored 384^3 runs and
+their FP32 reference, the one-rank slab, implicit Smagorinsky, D3Q15, D2Q9, the power-law
+channel, the adjoint, the Yu/Chai cost comparison of Section 5.2): each is warmed up for at
+least 0.2 s and timed over at least 0.25 s, whatever --steps is. ``cpu_baseline`` times the
+FP64 oracle, single-threaded, on a bounded slab of the same workload and on the full 32^3
+Taylor-Green parity run.
 
     python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
 """
@@ -24,9 +31,11 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
+from contextlib import nullcontext
 from pathlib import Path
 
 ROOT = Path(__file__).resolve().parent
@@ -45,9 +54,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_sha() -> str:
+# ... and, with the strain query kernel, those of the Section 5.2 comparison
+STRAIN_SOURCES = KERNEL_SOURCES + ["paper_1704_07559_amd/csrc/kernels_d3q19.hip"]
+
+
+def kernel_source_sha(sources=None) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources or KERNEL_SOURCES:
         h.update((ROOT / rel).read_bytes())
     return h.hexdigest()[:16]
 
@@ -122,48 +135,122 @@ def les_params(capi, n, storage):
                        nu0=(tau0 - 0.5) / 3.0, c_smag=0.1)
 
 
-def time_run(sim, steps, warmup, reduce_every=100, windows=None, sample_every=10):
-    """Run warmup + timed steps; returns (wall seconds, mean kernel seconds, last diagnostics).
-    The diagnostics run every ``reduce_every`` steps inside the timed region without stalling
-    the stream (lbm_reduce_async into pinned host slots, one per check); every check is read
-    and verified once the run has finished. The kernel time is the mean over every
-    ``sample_every``-th launch of the timed region, each bracketed by HIP events on the launch
-    stream (events on every launch would add their own gaps to the run). With ``windows`` = a
-    list, it also receives the device time per step (ms) of each run of ``reduce_every``
-    steps (events at the window edges)."""
+def settle(torch, capi, seconds=0.25):
+    """Keep the device busy with STREAM-style copies of 256 MiB for ``seconds`` before a timed
+    leg, so that it does not start from a GPU left idle by host-side setup."""
+    a = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            capi.lbm_stream_copy(a, b, a.numel() * 4, stream)
+        torch.cuda.synchronize()
+    del a, b
+
+
+def time_run(sim, steps, warmup, reduce_every=100, windows=None, min_warm_s=0.0, min_span_s=0.0):
+    """Run ``warmup`` untimed steps, then a timed run; returns a dict with the wall time, the
+    kernel time per launch, the number of timed steps and checks, and the last diagnostics.
+
+    ``min_warm_s``: keep warming up (in runs of 10 steps) until that much wall time has passed.
+    ``min_span_s``: lengthen the timed run to at least that much device time (estimated from 10
+    launches), so that the measurement does not depend on ``steps`` being large.
+    The diagnostics run after every ``reduce_every`` steps inside the timed region, without
+    stalling the stream (lbm_reduce_async into pinned host slots, read once the run has
+    finished); a run shorter than that has none inside, and is checked once after the timing.
+    HIP events on the launch stream bracket every run of launches between two reductions; the
+    kernel time is their summed device time over the number of launches (the reductions are
+    outside the brackets, the gaps between back-to-back launches inside). ``windows`` (a list)
+    receives the device time per step (ms) of each full window."""
     import torch
     sim.step(warmup)
     torch.cuda.synchronize()
-    sampled = list(range(0, steps, sample_every))
-    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
-    edge_ev = [torch.cuda.Event(enable_timing=True) for _ in range(0, steps, reduce_every)]
-    nchecks = steps // reduce_every
-    slots = torch.zeros((max(nchecks, 1), 8), dtype=torch.float64, pin_memory=True)
+    t0 = time.perf_counter()
+    extra_warm = 0
+    while time.perf_counter() - t0 < min_warm_s:
+        sim.step(10)
+        extra_warm += 10
+        torch.cuda.synchronize()
+    if min_span_s > 0.0:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(10)
+        e1.record()
+        torch.cuda.synchronize()
+        extra_warm += 10
+        est = e0.elapsed_time(e1) / 1e3 / 10
+        steps = max(steps, int(math.ceil(min_span_s / est)))
+    bounds = list(range(0, steps, reduce_every)) + [steps]
+    chunks = list(zip(bounds[:-1], bounds[1:]))
+    checks = steps // reduce_every
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in chunks]
+    slots = torch.zeros((max(checks, 1), 8), dtype=torch.float64, pin_memory=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        if k % reduce_every == 0:
-            edge_ev[k // reduce_every].record()
-        if k in ev:
-            ev[k][0].record()
-            sim.step(1)
-            ev[k][1].record()
-        else:
-            sim.step(1)
-        if (k + 1) % reduce_every == 0:
-            sim.reduce_async(slots[(k + 1) // reduce_every - 1])
+    for c, ((a, b), (e0, e1)) in enumerate(zip(chunks, ev)):
+        e0.record()
+        sim.step(b - a)
+        e1.record()
+        if b - a == reduce_every:
+            sim.reduce_async(slots[c])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern = sum(a.elapsed_time(b) for a, b in ev.values()) / len(ev) / 1e3
+    dev = [e0.elapsed_time(e1) / 1e3 for e0, e1 in ev]
+    kern = sum(dev) / steps
     if windows is not None:
-        for a, b in zip(edge_ev[:-1], edge_ev[1:]):
-            windows.append(a.elapsed_time(b) / reduce_every)
-    if nchecks == 0:
-        return wall, kern, sim.reduce(allow_nonfinite=True)
-    bad = [i for i in range(nchecks) if slots[i, 7].item() != 0.0]
+        for (a, b), d in zip(chunks, dev):
+            if b - a == reduce_every:
+                windows.append(d * 1e3 / reduce_every)
+    bad = [i for i in range(checks) if slots[i, 7].item() != 0.0]
     if bad:
-        log(f"non-finite populations at check {bad[0]} ({(bad[0] + 1) * reduce_every} steps)")
-    return wall, kern, sim.diagnostics(slots[nchecks - 1].tolist())
+        log(f"non-finite populations at check {bad[0]} (step {chunks[bad[0]][1]})")
+    last = sim.diagnostics(slots[checks - 1].tolist()) if checks == len(chunks) else sim.reduce(allow_nonfinite=True)
+    return {"wall": wall, "kernel_s": kern, "steps": steps, "warmup": warmup + extra_warm, "checks": checks,
+            "diag": last}
+
+
+# Extra legs: untimed warm-up of at least 0.2 s and a timed span of at least 0.25 s of device
+# time, whatever --steps and --warmup are.
+LEG_WARM_S = 0.2
+LEG_SPAN_S = 0.25
+
+
+def leg(torch, capi, sim, nodes, steps, warmup, bytes_per_node, **extra):
+    """Time one extra workload (settled device, minimum warm-up and span) and summarise it."""
+    settle(torch, capi)
+    r = time_run(sim, steps, warmup, min_warm_s=LEG_WARM_S, min_span_s=LEG_SPAN_S)
+    out = {"MLUPS": round(nodes * r["steps"] / r["wall"] / 1e6, 1),
+           "ms_per_step": round(r["wall"] / r["steps"] * 1e3, 4),
+           "kernel_ms": round(r["kernel_s"] * 1e3, 4), "bytes_per_node": bytes_per_node,
+           "hbm_frac": round(bytes_per_node * nodes / r["kernel_s"] / 1e9 / HBM_PEAK_GBS, 4),
+           "steps": r["steps"], "warmup": r["warmup"], "checks": r["checks"],
+           "ke": r["diag"]["ke"], "nonfinite": r["diag"]["nonfinite"]}
+    out.update(extra)
+    return out, r
+
+
+def step_kernel_name(nx, ny, storage="f32", walls=False, corrected=False):
+    """The D3Q19 step kernel instance the library launches for a box (its launch rule restated:
+    rows split into segments of the widest power of two <= 256 dividing nx when nx is a
+    multiple of 64, else one masked segment; pull mode 2 (whole rows, LDS exchange) when one
+    block holds whole rows of >= 64 nodes and its rows tile ny, 1 when a segment covers the
+    row, 0 for part rows)."""
+    tx = 256
+    if nx % 64 == 0:
+        while nx % tx:
+            tx //= 2
+    else:
+        tx = 1
+        while tx < nx and tx < 256:
+            tx *= 2
+    py = 1
+    while py < ny:
+        py *= 2
+    ty = min(256 // tx, py)
+    mode = 2 if (tx == nx and tx >= 64 and ny % ty == 0) else (1 if tx >= nx else 0)
+    st = {"f32": "float", "f16": "_Float16", "bf16": "__bf16"}[storage]
+    return f"lbm::d3q19::step_kernel<{st}, {str(walls).lower()}, {mode}, {str(corrected).lower()}>"
 
 
 def channel_runs(torch, capi, lbm, steps, warmup):
@@ -179,18 +266,19 @@ def channel_runs(torch, capi, lbm, steps, warmup):
                         visc_kind=capi.LBM_VISC_POWERLAW, visc_strain=capi.LBM_STRAIN_CHAI,
                         K_pl=0.1 * gref ** (1 - n_pl), n_pl=n_pl, nu_min=1e-3, nu_max=1.0)
         sim = lbm.LBM(p)
-        log(f"power-law channel n={n_pl}: {warmup} warmup + {steps} timed steps")
-        wall, kern, diag = time_run(sim, steps, warmup)
+        log(f"power-law channel n={n_pl}")
+        o, r = leg(torch, capi, sim, N, steps, warmup, 160, umax=None,
+                   kernel=step_kernel_name(nx, ny, walls=True))
+        o["umax"] = r["diag"]["umax"]
         sim.close()
-        out[f"n{n_pl}"] = {"MLUPS": round(N * steps / wall / 1e6, 1), "kernel_ms": round(kern * 1e3, 4),
-                           "hbm_frac": round(160 * N / kern / 1e9 / HBM_PEAK_GBS, 4),
-                           "umax": diag["umax"], "nonfinite": diag["nonfinite"]}
+        out[f"n{n_pl}"] = o
     torch.cuda.empty_cache()
     return out
 
 
 def _event_time(torch, fn, reps):
-    """Mean device time of fn() over reps calls (events on the current stream)."""
+    """Mean device time of fn() over reps back-to-back calls (events on the current stream),
+    after one untimed call."""
     fn()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -202,29 +290,102 @@ def _event_time(torch, fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def other_kernels(torch, np, synth, capi, lbm, u, steps, warmup):
-    """The remaining kernels of the path, each against its algorithmic bytes per node:
-    the D3Q19 step emitting the Chai strain every step (160 + 24 B), the strain query
-    (76 + 4 + 24 B), the diagnostics reduction (76 + 4 B read) on the 256^3 LES state, and the
-    D2Q9 LES step on 4096^2 (9 x 4 x 2 + 8 = 80 B)."""
+# Section 5.2 counts the operations of one node's strain: Chai's formula 957 multiplications
+# and 792 additions, Yu's 155 and 113 (dense 19 x 19 products).
+PAPER_OPS = {"yu": 155 + 113, "chai": 957 + 792}
+
+
+def strain_formulas(torch, np, capi, lbm, u, reps, sha):
+    """Yu against Chai on the chip (the operation counts of Section 5.2): on the 256^3 LES state,
+    the strain query (lbm_strain, 76 + 4 B read, 24 B written per node) with either formula,
+    the LES step emitting either strain every step (160 + 24 B), and the LES step whose
+    viscosity is driven by either formula without emitting it (160 B). Device time per call
+    over ``reps`` back-to-back calls; VALU instructions per wave from the committed counter
+    summary (profiles/valu_strain_formulas.txt) when it was taken on the current kernels."""
+    n = u.shape[1]
+    N = n ** 3
+    out = {}
+    rho_u = lbm.rho_u_field(np.zeros((n, n, n)), u)
+    sims = {}
+    for drive, kind in (("yu", capi.LBM_STRAIN_YU), ("chai", capi.LBM_STRAIN_CHAI)):
+        p = les_params(capi, n, capi.LBM_F32)
+        p.visc_strain = kind
+        sims[drive] = lbm.LBM(p, rho_u)
+    del rho_u
+    S = torch.empty((6, n, n, n), device="cuda")
+    yu = sims["yu"]
+    settle(torch, capi)
+    yu.step(20)
+    t = {}
+    for name, kind in (("yu", capi.LBM_STRAIN_YU), ("chai", capi.LBM_STRAIN_CHAI)):
+        t[f"query_{name}"] = _event_time(torch, lambda k=kind: capi.lbm_strain(yu.ctx, k, S), reps)
+    for name, kind in (("yu", capi.LBM_STRAIN_YU), ("chai", capi.LBM_STRAIN_CHAI)):
+        t[f"step_emit_{name}"] = _event_time(torch, lambda k=kind: yu.step(1, S_out=S, strain_kind=k), reps)
+    for name in ("yu", "chai"):
+        sims[name].step(20)
+        t[f"step_drive_{name}"] = _event_time(torch, lambda s=sims[name]: s.step(1), reps)
+    for s_ in sims.values():
+        s_.close()
+    del S, sims
+    torch.cuda.empty_cache()
+    bpn = {"query": 104, "step_emit": 184, "step_drive": 160}
+    valu = read_valu_strain(sha)
+    for key, sec in t.items():
+        kind = key.rsplit("_", 1)[0]
+        out[key] = {"kernel_ms": round(sec * 1e3, 4), "bytes_per_node": bpn[kind],
+                    "hbm_frac": round(bpn[kind] * N / sec / 1e9 / HBM_PEAK_GBS, 4)}
+        if valu and key in valu:
+            out[key]["valu_per_wave"] = round(valu[key], 1)
+    ratios = {}
+    for kind in ("query", "step_emit", "step_drive"):
+        r = {"time": round(t[f"{kind}_chai"] / t[f"{kind}_yu"], 4)}
+        if valu and f"{kind}_chai" in valu and f"{kind}_yu" in valu:
+            r["valu"] = round(valu[f"{kind}_chai"] / valu[f"{kind}_yu"], 4)
+        ratios[kind] = r
+    out["chai_over_yu"] = ratios
+    out["paper_ops_per_node"] = {"yu": PAPER_OPS["yu"], "chai": PAPER_OPS["chai"],
+                                 "chai_over_yu": round(PAPER_OPS["chai"] / PAPER_OPS["yu"], 4)}
+    return out
+
+
+def read_valu_strain(sha: str):
+    """VALU instructions per wave of the Section 5.2 comparison kernels from the committed
+    counter summary, if it was taken on the current kernel source (else None)."""
+    f = ROOT / "profiles" / "valu_strain_formulas.txt"
+    if not f.exists():
+        return None
+    kv = {}
+    for line in f.read_text().splitlines():
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != sha:
+        return None
+    out = {}
+    for k, v in kv.items():
+        if k.endswith("_valu_per_wave"):
+            try:
+                out[k[: -len("_valu_per_wave")]] = float(v)
+            except ValueError:
+                pass
+    return out or None
+
+
+def other_kernels(torch, np, synth, capi, lbm, u, reps, steps, warmup):
+    """The remaining kernels of the path, each against its algorithmic bytes per node: the
+    diagnostics reduction (76 + 4 B read) on the 256^3 LES state, and the D2Q9 LES step on
+    4096^2 (9 x 4 x 2 + 8 = 80 B)."""
     out = {}
     n = u.shape[1]
     N = n ** 3
     sim = lbm.LBM(les_params(capi, n, capi.LBM_F32), lbm.rho_u_field(np.zeros((n, n, n)), u))
-    S = torch.empty((6, n, n, n), device="cuda")
     sim.step(warmup)
-    t = _event_time(torch, lambda: sim.step(1, S_out=S, strain_kind=capi.LBM_STRAIN_CHAI), steps)
-    out["step_with_chai_strain_256"] = {"kernel_ms": round(t * 1e3, 4), "bytes_per_node": 184,
-                                        "hbm_frac": round(184 * N / t / 1e9 / HBM_PEAK_GBS, 4)}
-    t = _event_time(torch, lambda: capi.lbm_strain(sim.ctx, capi.LBM_STRAIN_YU, S), 50)
-    out["strain_query_256"] = {"kernel_ms": round(t * 1e3, 4), "bytes_per_node": 104,
-                               "hbm_frac": round(104 * N / t / 1e9 / HBM_PEAK_GBS, 4)}
     t = _event_time(torch, lambda: sim.reduce(), 20)
     out["diagnostics_reduce_256"] = {"call_ms": round(t * 1e3, 4), "bytes_per_node": 80,
                                      "hbm_frac": round(80 * N / t / 1e9 / HBM_PEAK_GBS, 4),
                                      "note": "includes the final pass and the host copy"}
     sim.close()
-    del sim, S
+    del sim
     torch.cuda.empty_cache()
     m = 4096
     u2 = synth.spectrum_velocity((1, m, m), seed=1704, u_rms=0.04)[:2]
@@ -233,13 +394,10 @@ def other_kernels(torch, np, synth, capi, lbm, u, steps, warmup):
                      visc_kind=capi.LBM_VISC_SMAGORINSKY, visc_strain=capi.LBM_STRAIN_YU,
                      nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
     s2 = lbm.LBM(p2, lbm.rho_u_field(np.zeros((1, m, m)), u2))
-    log(f"D2Q9 {m}^2 LES: {warmup} warmup + {steps} timed steps")
-    w2, k2, d2 = time_run(s2, steps, warmup)
+    log(f"D2Q9 {m}^2 LES")
+    out["d2q9_les_4096sq"], _ = leg(torch, capi, s2, m * m, steps, warmup, 80)
     s2.close()
     torch.cuda.empty_cache()
-    out["d2q9_les_4096sq"] = {"MLUPS": round(m * m * steps / w2 / 1e6, 1), "kernel_ms": round(k2 * 1e3, 4),
-                              "bytes_per_node": 80, "hbm_frac": round(80 * m * m / k2 / 1e9 / HBM_PEAK_GBS, 4),
-                              "nonfinite": d2["nonfinite"]}
     return out
 
 
@@ -359,38 +517,43 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(u_full, n_slab=64, steps=6, steps_1t=2):
-    """FP64 oracle on a 256 x 256 x n_slab z-slab of the same initial field (periodic in the
-    slab), Smagorinsky from Yu: ``steps`` steps with the BLAS thread pool as configured, then
-    ``steps_1t`` steps with one thread."""
+def cpu_baseline(u_full, n_slab=64, steps=6):
+    """The FP64 oracle as it stands, on one host thread (its element-wise NumPy work runs on
+    one core; more BLAS threads gain little): ``steps`` steps of a 256 x 256 x n_slab z-slab of
+    the headline field (periodic in the slab, Smagorinsky from Yu), and the full 32^3 rotated
+    Taylor-Green parity run (200 steps, both strains every step)."""
     import numpy as np
+
+    import synth
     from oracle import d3q19 as od
     try:
-        from threadpoolctl import threadpool_info, threadpool_limits
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
+        from threadpoolctl import threadpool_limits
+    except Exception:   # pragma: no cover
         threadpool_limits = None
-        threads = os.cpu_count() or 1
     u = np.ascontiguousarray(u_full[:, :n_slab])
     shape = u.shape[1:]
     tau0 = 0.51
     p = od.Params(s=od.default_rates(tau0), visc_kind="smagorinsky", visc_strain="yu", nu0=(tau0 - 0.5) / 3.0,
                   c_smag=0.1)
     sim = od.Simulation(p, od.init_populations(np.zeros(shape), u, p))
-    t0 = time.perf_counter()
-    sim.step(steps)
-    dt = time.perf_counter() - t0
+    c0 = (32, 32, 32)
+    drho, u0, grad = synth.tgv_rotated(c0, u0=0.05)
+    p0 = od.Params(s=od.default_rates(0.8))
+    tgv = od.Simulation(p0, od.init_populations(drho, u0, p0, grad))
+    with (threadpool_limits(limits=1) if threadpool_limits is not None else nullcontext()):
+        t0 = time.perf_counter()
+        sim.step(steps)
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        tgv.step(200)
+        dt0 = time.perf_counter() - t0
     nodes = int(np.prod(shape))
-    out = {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-           "sample": f"FP64 NumPy oracle, {shape[2]}x{shape[1]}x{shape[0]} z-slab of the 256^3 workload, "
-                     f"{steps} steps, {dt:.1f} s", "cpu_model": _cpu_model()}
-    if threadpool_limits is not None and steps_1t > 0:
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            sim.step(steps_1t)
-            dt1 = time.perf_counter() - t0
-        out["single_thread_value"] = nodes * steps_1t / dt1 / 1e6
-    return out
+    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle on one thread, {shape[2]}x{shape[1]}x{shape[0]} z-slab of the 256^3 "
+                      f"workload, {steps} steps, {dt:.1f} s",
+            "cpu_model": _cpu_model(),
+            "c0_full_run": {"grid": "32^3 rotated Taylor-Green", "steps": 200, "seconds": round(dt0, 2),
+                            "MLUPS": round(32 ** 3 * 200 / dt0 / 1e6, 3)}}
 
 
 def main():
@@ -399,10 +562,15 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="edge of the cubic LES box (default 256)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 384^3 FP16/BF16/FP32 storage runs")
+    ap.add_argument("--no-extra", action="store_true", help="skip every workload but the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage-probe", choices=("f16", "bf16", "f32"),
                     help="only step the 384^3 LES in that storage (--steps steps; counter collection)")
+    ap.add_argument("--slab-probe", action="store_true",
+                    help="only step the 384x384x48 FP16 slab (--steps steps; counter collection)")
+    ap.add_argument("--strain-probe", action="store_true",
+                    help="only run the Section 5.2 kernels on the 256^3 LES state, 5 calls each in a fixed "
+                         "order (counter collection)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -431,17 +599,49 @@ def main():
     import synth
     from paper_1704_07559_amd import capi, lbm
 
-    if args.storage_probe:
+    if args.storage_probe or args.slab_probe:
         m = 384
-        st = {"f16": capi.LBM_F16, "bf16": capi.LBM_BF16, "f32": capi.LBM_F32}[args.storage_probe]
+        st = capi.LBM_F16 if args.slab_probe else {"f16": capi.LBM_F16, "bf16": capi.LBM_BF16,
+                                                   "f32": capi.LBM_F32}[args.storage_probe]
         u3 = synth.spectrum_velocity((m, m, m), seed=1704, u_rms=0.04)
-        sim = lbm.LBM(les_params(capi, m, st), lbm.rho_u_field(np.zeros((m, m, m)), u3))
+        p = les_params(capi, m, st)
+        if args.slab_probe:
+            p.nz = m // 8
+            u3 = np.ascontiguousarray(u3[:, : m // 8])
+        sim = lbm.LBM(p, lbm.rho_u_field(np.zeros(u3.shape[1:]), u3))
         del u3
         sim.step(args.warmup + args.steps)
         d = sim.reduce(allow_nonfinite=True)
         sim.close()
-        print(json.dumps({"storage_probe": args.storage_probe, "steps": args.warmup + args.steps,
-                          "nonfinite": d["nonfinite"]}))
+        print(json.dumps({"probe": "slab" if args.slab_probe else args.storage_probe,
+                          "steps": args.warmup + args.steps, "nonfinite": d["nonfinite"]}))
+        return
+
+    if args.strain_probe:
+        n = args.n
+        u = synth.spectrum_velocity((n, n, n), seed=1704, u_rms=0.04)
+        rho_u = lbm.rho_u_field(np.zeros((n, n, n)), u)
+        del u
+        sims = {}
+        for drive, kind in (("yu", capi.LBM_STRAIN_YU), ("chai", capi.LBM_STRAIN_CHAI)):
+            p = les_params(capi, n, capi.LBM_F32)
+            p.visc_strain = kind
+            sims[drive] = lbm.LBM(p, rho_u)
+        S = torch.empty((6, n, n, n), device="cuda")
+        # dispatch order (the counter summary splits the records by it): 5 queries Yu, 5 Chai,
+        # 5 steps emitting Yu, 5 emitting Chai, 5 steps driven by Yu, 5 driven by Chai
+        for kind in (capi.LBM_STRAIN_YU, capi.LBM_STRAIN_CHAI):
+            for _ in range(5):
+                capi.lbm_strain(sims["yu"].ctx, kind, S)
+        for kind in (capi.LBM_STRAIN_YU, capi.LBM_STRAIN_CHAI):
+            for _ in range(5):
+                sims["yu"].step(1, S_out=S, strain_kind=kind)
+        for drive in ("yu", "chai"):
+            sims[drive].step(5)
+        torch.cuda.synchronize()
+        for s_ in sims.values():
+            s_.close()
+        print(json.dumps({"probe": "strain", "n": n}))
         return
 
     n = args.n
@@ -452,11 +652,13 @@ def main():
     del rho_u
     N = n ** 3
     log(f"FP32 {n}^3: {args.warmup} warmup + {args.steps} timed steps")
+    settle(torch, capi)
     win = []
-    wall, kern, diag = time_run(sim, args.steps, args.warmup, windows=win)
+    r = time_run(sim, args.steps, args.warmup, windows=win)
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    wall, kern, diag = r["wall"], r["kernel_s"], r["diag"]
     mlups = N * args.steps / wall / 1e6
     bytes_per_node = 19 * 4 * 2 + 4 * 2
     achieved = bytes_per_node * N / kern / 1e9
@@ -477,24 +679,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D3Q19 He-Luo MRT LES {n}^3 periodic, FP32 populations, Smagorinsky C_s=0.1 "
                                f"from the Yu strain, k^4 exp(-2(k/4)^2) spectrum seed 1704 u_rms 0.04, "
-                               f"diagnostics every 100 steps",
+                               f"FP64 diagnostics after every 100 steps inside the timed region "
+                               f"({r['checks']} in this run)",
                    "nodes": N, "lattice": "D3Q19", "storage": "f32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "lbm::d3q19::step_kernel<float, false, 2, false>",
-                     "kernel_ms": round(kern * 1e3, 4), "bytes_per_node": bytes_per_node,
-                     "kernel_source_sha": sha,
+                     "traffic": traffic, "kernel": step_kernel_name(n, n),
+                     "kernel_ms": round(kern * 1e3, 4), "kernel_time": "device time of all timed launches / launches",
+                     "bytes_per_node": bytes_per_node, "kernel_source_sha": sha,
                      "valu_issue_frac": valu_frac(read_valu("f32_les256", sha) if n == 256 else None, kern)},
         "diagnostics": {"mass": diag["mass"], "ke": diag["ke"], "umax": diag["umax"], "nonfinite": diag["nonfinite"]},
     }
     if win:
-        # device time of consecutive 100-step windows (each includes its diagnostics reduction)
         wm = sorted(N / (w * 1e-3) / 1e6 for w in win)
         result["windows_MLUPS"] = {"count": len(wm), "min": round(wm[0], 1), "median": round(wm[len(wm) // 2], 1),
                                    "max": round(wm[-1], 1)}
 
     if not args.no_extra:
         extra = {}
+        K, W = args.steps, args.warmup
         m = 384
         log(f"generating the {m}^3 initial field")
         u3 = synth.spectrum_velocity((m, m, m), seed=1704, u_rms=0.04)
@@ -503,19 +706,14 @@ def main():
         for name, st, bpn in (("f16", capi.LBM_F16, 19 * 2 * 2 + 8), ("bf16", capi.LBM_BF16, 19 * 2 * 2 + 8),
                               ("f32", capi.LBM_F32, 19 * 4 * 2 + 8)):
             s3 = lbm.LBM(les_params(capi, m, st), rho_u3)
-            steps3 = max(1, args.steps // 2)
-            log(f"{name} {m}^3: {args.warmup} warmup + {steps3} timed steps")
-            w3, k3, d3 = time_run(s3, steps3, args.warmup)
+            log(f"{name} {m}^3")
+            o, r3 = leg(torch, capi, s3, m ** 3, K, W, bpn, kernel=step_kernel_name(m, m, name))
+            if name == "f16":
+                o["valu_issue_frac"] = valu_frac(read_valu("f16_les384", sha), r3["kernel_s"])
+            extra[f"les384_{name}"] = o
             s3.close()
             del s3
             torch.cuda.empty_cache()
-            extra[f"les384_{name}"] = {"MLUPS": round(m ** 3 * steps3 / w3 / 1e6, 1),
-                                       "ms_per_step": round(w3 / steps3 * 1e3, 4),
-                                       "kernel_ms": round(k3 * 1e3, 4), "bytes_per_node": bpn,
-                                       "hbm_frac": round(bpn * m ** 3 / k3 / 1e9 / HBM_PEAK_GBS, 4),
-                                       "ke": d3["ke"], "nonfinite": d3["nonfinite"]}
-            if name == "f16":
-                extra[f"les384_{name}"]["valu_issue_frac"] = valu_frac(read_valu("f16_les384", sha), k3)
         # one rank's share of a z-slab decomposition of the 384^3 FP16 run over 8 GPUs: the
         # 384 x 384 x 48 interior, updated by the same kernel (its faces wrap periodically
         # here; a decomposed run would read them from 2 ghost planes exchanged per step)
@@ -524,65 +722,46 @@ def main():
         ps.nz = zs
         slab = rho_u3.reshape(4, m, m, m)[:, :zs].contiguous()
         ss = lbm.LBM(ps, slab)
-        log(f"f16 {m}x{m}x{zs} slab: {args.warmup} warmup + {args.steps} timed steps")
-        wsl, ksl, dsl = time_run(ss, args.steps, args.warmup)
-        ss.close()
-        del ss, slab
+        log(f"f16 {m}x{m}x{zs} slab")
         halo = 2 * 5 * m * m * 2  # the 5 populations with c_z = +1 and the 5 with c_z = -1, FP16
-        extra["slab_384x384x48_f16"] = {"MLUPS": round(m * m * zs * args.steps / wsl / 1e6, 1),
-                                        "ms_per_step": round(wsl / args.steps * 1e3, 4),
-                                        "kernel_ms": round(ksl * 1e3, 4), "bytes_per_node": 84,
-                                        "hbm_frac": round(84 * m * m * zs / ksl / 1e9 / HBM_PEAK_GBS, 4),
-                                        "halo_bytes_per_step": halo, "nonfinite": dsl["nonfinite"]}
-        del rho_u3
+        extra["slab_384x384x48_f16"], _ = leg(torch, capi, ss, m * m * zs, K, W, 84, halo_bytes_per_step=halo,
+                                              kernel=step_kernel_name(m, m, "f16"))
+        ss.close()
+        del ss, slab, rho_u3
         torch.cuda.empty_cache()
         # the same 256^3 LES with the implicit (non-lagged) Smagorinsky coupling: no s_nu field
         pi = les_params(capi, n, capi.LBM_F32)
         pi.visc_kind = capi.LBM_VISC_SMAGORINSKY_IMPLICIT
         si = lbm.LBM(pi, lbm.rho_u_field(np.zeros((n, n, n)), u))
-        log(f"FP32 {n}^3 implicit Smagorinsky: {args.warmup} warmup + {args.steps} timed steps")
-        wi, ki, di = time_run(si, args.steps, args.warmup)
+        log(f"FP32 {n}^3 implicit Smagorinsky")
+        extra["les256_implicit_smagorinsky"], _ = leg(torch, capi, si, N, K, W, 152, kernel=step_kernel_name(n, n))
         si.close()
         del si
         torch.cuda.empty_cache()
-        extra["les256_implicit_smagorinsky"] = {"MLUPS": round(N * args.steps / wi / 1e6, 1),
-                                                "ms_per_step": round(wi / args.steps * 1e3, 4),
-                                                "kernel_ms": round(ki * 1e3, 4), "bytes_per_node": 152,
-                                                "hbm_frac": round(152 * N / ki / 1e9 / HBM_PEAK_GBS, 4),
-                                                "ke": di["ke"], "nonfinite": di["nonfinite"]}
         # the same LES on the D3Q15 lattice (Yu-type formula of the Section 5.4 route):
         # 15 x 4 B read + written + 8 B lagged s_nu = 128 B/node
         p15 = capi.Params(nx=n, ny=n, nz=n, lattice=capi.LBM_D3Q15, storage=capi.LBM_F32,
                           s=rates15(0.51) + [0.0] * 4, visc_kind=capi.LBM_VISC_SMAGORINSKY,
                           visc_strain=capi.LBM_STRAIN_YU, nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
         s15 = lbm.LBM(p15, lbm.rho_u_field(np.zeros((n, n, n)), u))
-        log(f"D3Q15 FP32 {n}^3 LES: {args.warmup} warmup + {args.steps} timed steps")
-        w15, k15, d15 = time_run(s15, args.steps, args.warmup)
+        log(f"D3Q15 FP32 {n}^3 LES")
+        extra["les256_d3q15"], _ = leg(torch, capi, s15, N, K, W, 128)
         s15.close()
         del s15
         torch.cuda.empty_cache()
-        extra["les256_d3q15"] = {"MLUPS": round(N * args.steps / w15 / 1e6, 1),
-                                 "ms_per_step": round(w15 / args.steps * 1e3, 4),
-                                 "kernel_ms": round(k15 * 1e3, 4), "bytes_per_node": 128,
-                                 "hbm_frac": round(128 * N / k15 / 1e9 / HBM_PEAK_GBS, 4),
-                                 "ke": d15["ke"], "nonfinite": d15["nonfinite"]}
+        extra["channel_powerlaw"] = channel_runs(torch, capi, lbm, K, W)
+        extra["strain_formulas_256"] = strain_formulas(torch, np, capi, lbm, u, 50, kernel_source_sha(STRAIN_SOURCES))
+        extra["adjoint_c4"] = adjoint_run(torch, np, synth, capi, lbm, W)
+        torch.cuda.empty_cache()
+        extra["adjoint_c4_smagorinsky"] = adjoint_run(torch, np, synth, capi, lbm, W, visc="smagorinsky")
+        extra["other_kernels"] = other_kernels(torch, np, synth, capi, lbm, u, 20, K, W)
+        cp = copy_bandwidth(torch, capi)
+        extra.update(cp)
+        extra["step_over_stream_copy"] = round(result["roofline"]["achieved"] / cp["stream_copy_GBps"], 4)
         result["extra"] = extra
 
-    if not args.no_extra:
-        result.setdefault("extra", {})
-        result["extra"]["channel_powerlaw"] = channel_runs(torch, capi, lbm, max(1, args.steps // 2), args.warmup)
-        result["extra"]["adjoint_c4"] = adjoint_run(torch, np, synth, capi, lbm, args.warmup)
-        torch.cuda.empty_cache()
-        result["extra"]["adjoint_c4_smagorinsky"] = adjoint_run(torch, np, synth, capi, lbm, args.warmup,
-                                                                visc="smagorinsky")
-        result["extra"]["other_kernels"] = other_kernels(torch, np, synth, capi, lbm, u, max(1, args.steps // 5),
-                                                         args.warmup)
-        cp = copy_bandwidth(torch, capi)
-        result["extra"].update(cp)
-        result["extra"]["step_over_stream_copy"] = round(result["roofline"]["achieved"] / cp["stream_copy_GBps"], 4)
-
     if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on a slab")
+        log("timing the FP64 oracle on one thread")
         result["cpu_baseline"] = cpu_baseline(u)
     print(json.dumps(result), flush=True)
 

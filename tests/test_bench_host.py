@@ -43,3 +43,21 @@ def test_valu_record_matches_only_its_kernel_source():
     assert bench.valu_frac(None, 1e-3) is None
     # the issue ceiling: 614.4e9 wave instructions per second
     assert abs(bench.valu_frac(614.4e6, 1e-3) - 1.0) < 1e-9
+
+
+def test_step_kernel_name_follows_the_launch_rule():
+    """The instance named in the roofline record: whole 256-node rows exchange through LDS
+    (pull mode 2), 384-node rows split into 128-node segments (mode 0), rows of 32 nodes are
+    covered by one masked block (mode 1), the 128-wide channel with walls is mode 2."""
+    assert bench.step_kernel_name(256, 256) == "lbm::d3q19::step_kernel<float, false, 2, false>"
+    assert bench.step_kernel_name(384, 384, "f16") == "lbm::d3q19::step_kernel<_Float16, false, 0, false>"
+    assert bench.step_kernel_name(384, 384, "bf16") == "lbm::d3q19::step_kernel<__bf16, false, 0, false>"
+    assert bench.step_kernel_name(32, 32) == "lbm::d3q19::step_kernel<float, false, 1, false>"
+    assert bench.step_kernel_name(128, 128, walls=True) == "lbm::d3q19::step_kernel<float, true, 2, false>"
+    assert bench.step_kernel_name(64, 6) == "lbm::d3q19::step_kernel<float, false, 1, false>"  # 4 rows do not tile 6
+
+
+def test_strain_valu_record_matches_only_its_kernel_sources():
+    v = bench.read_valu_strain(bench.kernel_source_sha(bench.STRAIN_SOURCES))
+    assert v is None or (v["query_chai"] > v["query_yu"] and v["step_drive_chai"] > v["step_drive_yu"])
+    assert bench.read_valu_strain("0" * 16) is None
