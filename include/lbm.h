@@ -183,7 +183,11 @@ lbm_status lbm_strain(lbm_ctx* ctx, int strain_kind, float* S_out, void* stream)
 
 /*
  * Global diagnostics of the current state, accumulated in FP64 with a deterministic
- * two-pass reduction. host_out (host memory, 8 doubles):
+ * two-pass reduction. The collision conserves mass and momentum exactly (the conserved rows
+ * of Eq. solvem, Eq. continuityandmomentum: delta-rho and j are unchanged by the relaxation,
+ * and the Guo force adds F per node and step), so [0] and [1..3] watch the run's round-off;
+ * [5] is the dissipation measure the strain formulas (Eq. LuoS, Eq. ChaiS) feed.
+ * host_out (host memory, 8 doubles):
  *   [0] sum delta_rho  [1..3] sum j (j includes F/2)  [4] sum |j|^2/(2 rho0)
  *   [5] sum S:S (Yu, off-diagonals counted twice)  [6] max |j|/rho0  [7] count of
  *   non-finite populations.
