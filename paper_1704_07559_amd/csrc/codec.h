@@ -21,6 +21,10 @@ __device__ __forceinline__ void stream_store(T* p, T v) {
 template <typename S>
 struct Codec;
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 template <>
 struct Codec<float> {
   static __device__ __forceinline__ float load_cached(const float* p) { return *p; }
@@ -34,6 +38,11 @@ struct Codec<_Float16> {
   static __device__ __forceinline__ float load(const _Float16* p) { return static_cast<float>(stream_load(p)); }
   // fptrunc float -> half rounds to nearest even (default rounding mode).
   static __device__ __forceinline__ void store(_Float16* p, float v) { stream_store(p, static_cast<_Float16>(v)); }
+  // Two values rounded by one packed conversion: a in the low half, b in the high half.
+  // (Taken apart as a 32-bit word: element access on the converted vector is avoided.)
+  static __device__ __forceinline__ unsigned encode2(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, f16x2));
+  }
 };
 
 template <>
@@ -42,6 +51,9 @@ struct Codec<__bf16> {
   static __device__ __forceinline__ float load(const __bf16* p) { return static_cast<float>(stream_load(p)); }
   // fptrunc float -> bfloat rounds to nearest even.
   static __device__ __forceinline__ void store(__bf16* p, float v) { stream_store(p, static_cast<__bf16>(v)); }
+  static __device__ __forceinline__ unsigned encode2(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
+  }
 };
 
 }  // namespace lbm

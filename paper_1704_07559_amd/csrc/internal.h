@@ -322,10 +322,27 @@ __device__ __forceinline__ void store_rows(S* __restrict__ dst, const Geo& G, co
                                            const float (&g)[Q]) {
   char* cb = reinterpret_cast<char*>(dst) + r.zb[1];
   const size_t run = static_cast<size_t>(G.nx) * sizeof(S);
-  static_for<Q>([&](auto ii) {
-    constexpr int i = ii;
-    store_at<S>(cb + i * run, r.self, g[i]);
-  });
+  if constexpr (sizeof(S) == 2) {
+    // 16-bit storage: one packed conversion rounds two populations (low and high half of
+    // one register, each stored from its half), and the lane offset is re-materialised next
+    // to the stores (the empty asm emits nothing) so that they take the scalar-base form
+    // instead of a 64-bit vector add each; 29 fewer VALU instructions per node. (For FP32
+    // storage the same addressing measured 1 % slower at 256^3, so FP32 keeps the plain form.)
+    unsigned self = r.self;
+    asm volatile("" : "+v"(self));
+    static_for<Q / 2>([&](auto pp) {
+      constexpr int i = 2 * pp;
+      const unsigned w = Codec<S>::encode2(g[i], g[i + 1]);
+      stream_store(reinterpret_cast<unsigned short*>(cb + i * run + self), static_cast<unsigned short>(w & 0xffffu));
+      stream_store(reinterpret_cast<unsigned short*>(cb + (i + 1) * run + self), static_cast<unsigned short>(w >> 16));
+    });
+    if constexpr (Q % 2 != 0) store_at<S>(cb + (Q - 1) * run, self, g[Q - 1]);
+  } else {
+    static_for<Q>([&](auto ii) {
+      constexpr int i = ii;
+      store_at<S>(cb + i * run, r.self, g[i]);
+    });
+  }
 }
 
 // Node index of (x, y, z) in the node-indexed fields (s_nu, forces, strain, canonical
