@@ -259,9 +259,10 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, int nsteps, const float* rec, float* 
  * array, not allocated by this call), so A*N*4 bytes must not exceed 64 MiB (A =
  * lbm_adjoint_planes: about 838 000 nodes with 20 planes). rec and grad_force as in
  * lbm_adjoint_steps; the result equals lbm_adjoint_steps' bit for bit. The call allocates
- * nothing: it validates, looks up the scratch address of the stream's device (once per
- * device), and queues the kernel launches and, for an odd nsteps, one device-to-device copy
- * into lam. Every call on one device shares that device's scratch, which keeps the last
+ * nothing: it validates, takes the scratch address of the stream's device (looked up once
+ * per device, by lbm_init on its stream's device or else by the first call here), and queues
+ * the kernel launches and, for an odd nsteps, one device-to-device copy into lam, so it can be
+ * captured into a HIP graph. Every call on one device shares that device's scratch, which keeps the last
  * call's contents (every step overwrites it whole, so nothing needs clearing): calls that
  * overlap on one device (several streams, several host threads) race and must be ordered by
  * the caller. Errors: LBM_EINVAL (NULL or misaligned pointers, nsteps < 0, the state larger

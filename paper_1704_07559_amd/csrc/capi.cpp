@@ -239,6 +239,11 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
     delete c;
     return hip_fail(e, "lbm_init");
   }
+  // Look up the allocation-free sweep's scratch on this stream's device now, so that a later
+  // lbm_adjoint_steps_noalloc (possibly under graph capture) finds it resolved. Not needed by
+  // anything else: a failure here is left for that entry point to report.
+  void* ignored = nullptr;
+  if (noalloc_scratch(s, &ignored) != hipSuccess) (void)hipGetLastError();
   *out = c;
   return LBM_OK;
 }
