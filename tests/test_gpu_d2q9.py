@@ -119,13 +119,13 @@ def test_taylor_green_64_squared_800_steps():
 @pytest.mark.slow
 def test_les_4096_squared_sampled():
     """The D2Q9 workload bench.py times (4096^2, FP32, Smagorinsky C_s = 0.1 from the Yu-type
-    strain, tau_nu0 = 0.51), in that launch configuration: two steps, then populations and
-    the strain of both steps at sampled nodes against the FP64 oracle run on each node's
-    5 x 5 neighbourhood (a node after k steps depends only on its radius-k neighbourhood)."""
+    strain, tau_nu0 = 0.51), in that launch configuration: 16 steps, then populations and
+    the strain of every step at sampled nodes against the FP64 oracle run on each node's
+    33 x 33 neighbourhood (a node after k steps depends only on its radius-k neighbourhood)."""
     import torch
     from paper_1704_07559_amd import capi, lbm
     from tests._common import sample_nodes
-    m, K = 4096, 2
+    m, K = 4096, 16
     shape = (1, m, m)
     u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)[:2]
     kw = dict(visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)

@@ -141,13 +141,13 @@ def test_half_precision_storage_against_oracle(storage, tol):
 @pytest.mark.slow
 def test_les_256_cubed_d3q15_sampled():
     """The D3Q15 LES workload bench.py times (256^3, FP32, Smagorinsky C_s = 0.1 from the
-    Yu-type strain, tau_nu0 = 0.51), in that launch configuration: two steps, then the
+    Yu-type strain, tau_nu0 = 0.51), in that launch configuration: 16 steps, then the
     populations and both strains at sampled nodes against the FP64 oracle run on each node's
     neighbourhood, Yu-type = Chai over the whole field, mass conservation."""
     import torch
     from paper_1704_07559_amd import capi, lbm
     from tests._common import patch_reference, sample_nodes
-    n, K = 256, 2
+    n, K = 256, 16
     shape = (n, n, n)
     u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
     kw = dict(visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)

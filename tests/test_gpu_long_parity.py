@@ -113,3 +113,46 @@ def test_200_steps_half_storage_is_the_rounded_fp32_step(storage):
     assert float(Sb.abs().max()) > 0.0
     a.close()
     b.close()
+
+
+# The D3Q15 and D2Q9 LES workloads: whole 256-node rows through LDS (D3Q15 at 256^3) and
+# 256-node segments of longer rows (D2Q9 at 4096^2, pull mode 0), 200 steps each.
+OTHER = {
+    "d3q15_les_rows256_lds": ("d3q15", (4, 4, 256)),
+    "d2q9_les_part_rows": ("d2q9", (1, 8, 512)),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("case", sorted(OTHER))
+def test_200_steps_other_lattices_against_oracle(case):
+    from paper_1704_07559_amd import capi, lbm
+    lattice, shape = OTHER[case]
+    if lattice == "d3q15":
+        from oracle import d3q15 as om
+        from tests.test_gpu_d3q15 import _spec
+        u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)
+        ncomp, wts = 6, np.array([1, 1, 1, 2, 2, 2], dtype=np.float64)
+    else:
+        from oracle import d2q9 as om
+        from tests.test_gpu_d2q9 import _spec
+        u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)[:2]
+        ncomp, wts = 3, np.array([1, 1, 2], dtype=np.float64)
+    import torch
+    op, cp = _spec(shape, tau=0.51, visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    ref = om.Simulation(op, om.init_populations(np.zeros(shape), u, op))
+    sim = lbm.LBM(cp, lbm.rho_u_field(np.zeros(shape), u))
+    S = torch.empty((ncomp,) + shape, device="cuda")
+    wts = wts.reshape((ncomp,) + (1,) * len(shape))
+    dS, scale, worst_pop, worst_snu = 0.0, 0.0, 0.0, 0.0
+    for n in range(1, STEPS + 1):
+        sim.step(1, S_out=S, strain_kind=capi.LBM_STRAIN_YU)
+        S_ref = ref.step(1)[0]
+        dS = max(dS, float(np.abs(to_np(S) - S_ref).max()))
+        scale = max(scale, float(np.sqrt((wts * S_ref**2).sum(axis=0)).max()))
+        if n % 10 == 0:
+            worst_pop = max(worst_pop, pop_rel_err(to_np(sim.populations()), ref.g, op.rho0, om.W))
+            snu = to_np(sim.s_nu).reshape(shape)
+            worst_snu = max(worst_snu, float(np.abs(snu - ref.s_nu).max() / np.abs(ref.s_nu).max()))
+    sim.close()
+    assert worst_pop < 1e-5 and dS / scale < 1e-4 and worst_snu < 1e-5, (worst_pop, dS / scale, worst_snu)
