@@ -114,25 +114,29 @@ def valu_frac(insts, kernel_s):
     return None if insts is None else round(insts / kernel_s / VALU_WAVE_INSTS_PER_S, 4)
 
 
+def _workloads():
+    from paper_1704_07559_amd import workloads
+    return workloads
+
+
 def rates(tau_nu):
-    # d'Humieres rates with s_nu = 1/tau_nu in slots 9, 11, 13, 14, 15
-    sn = 1.0 / tau_nu
-    return [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sn, 1.4, sn, 1.4, sn, sn, sn, 1.98, 1.98, 1.98]
+    """D3Q19 rates of the workloads (d'Humieres values, s_nu = 1/tau_nu in slots 9, 11, 13,
+    14, 15; paper_1704_07559_amd/configs records them per workload)."""
+    return _workloads().rates_d3q19(tau_nu)
 
 
 def rates15(tau_nu):
-    """D3Q15 relaxation rates (rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, p_ww, p_xy,
-    p_yz, p_xz, m_xyz): s_e = 1.6, s_eps = 1.2, s_q = 1.6, s_m = 1.2 (d'Humieres et al. 2002),
-    s_nu = 1/tau_nu."""
-    sn = 1.0 / tau_nu
-    return [0.0, 1.6, 1.2, 0.0, 1.6, 0.0, 1.6, 0.0, 1.6, sn, sn, sn, sn, sn, 1.2]
+    """D3Q15 rates (rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, p_ww, p_xy, p_yz, p_xz,
+    m_xyz): s_e = 1.6, s_eps = 1.2, s_q = 1.6, s_m = 1.2 (d'Humieres et al. 2002), s_nu = 1/tau_nu."""
+    return _workloads().rates_d3q15(tau_nu)
 
 
 def les_params(capi, n, storage):
-    tau0 = 0.51  # nu0 = 1/300
-    return capi.Params(nx=n, ny=n, nz=n, lattice=capi.LBM_D3Q19, storage=storage, s=rates(tau0),
-                       visc_kind=capi.LBM_VISC_SMAGORINSKY, visc_strain=capi.LBM_STRAIN_YU,
-                       nu0=(tau0 - 0.5) / 3.0, c_smag=0.1)
+    """The LES workload (configs/c1_les256.json; with FP16/BF16 storage the 384^3 one,
+    configs/c3_les384_half.json) on an n^3 box."""
+    w = _workloads()
+    name = {capi.LBM_F32: "f32", capi.LBM_F16: "f16", capi.LBM_BF16: "bf16"}[storage]
+    return w.params(w.load("C1"), storage=name, grid={"nx": n, "ny": n, "nz": n})
 
 
 def settle(torch, capi, seconds=0.25):
@@ -258,14 +262,12 @@ def channel_runs(torch, capi, lbm, steps, warmup):
     uniform body force 1e-6 along z, viscosity from the Chai strain, FP32, from rest; one
     run per index n. Algorithmic bytes per node: 160 (populations + lagged s_nu)."""
     out = {}
-    nx, ny, nz = 128, 128, 512
+    w = _workloads()
+    cfg = w.load("C2")
+    nx, ny, nz = cfg["grid"]["nx"], cfg["grid"]["ny"], cfg["grid"]["nz"]
     N = nx * ny * nz
-    gref = 1e-6 * ny / (2 * 0.1)   # wall shear rate of the Newtonian flow with nu = 0.1
-    for n_pl in (0.5, 1.0, 1.5):
-        p = capi.Params(nx=nx, ny=ny, nz=nz, s=rates(0.8), walls_y=1, force=(0.0, 0.0, 1e-6),
-                        visc_kind=capi.LBM_VISC_POWERLAW, visc_strain=capi.LBM_STRAIN_CHAI,
-                        K_pl=0.1 * gref ** (1 - n_pl), n_pl=n_pl, nu_min=1e-3, nu_max=1.0)
-        sim = lbm.LBM(p)
+    for n_pl in cfg["viscosity"]["n_pl"]:
+        sim = lbm.LBM(w.params(cfg, n_pl=n_pl))
         log(f"power-law channel n={n_pl}")
         o, r = leg(torch, capi, sim, N, steps, warmup, 160, umax=None,
                    kernel=step_kernel_name(nx, ny, walls=True))
@@ -389,10 +391,8 @@ def other_kernels(torch, np, synth, capi, lbm, u, reps, steps, warmup):
     torch.cuda.empty_cache()
     m = 4096
     u2 = synth.spectrum_velocity((1, m, m), seed=1704, u_rms=0.04)[:2]
-    sn = 1.0 / 0.51
-    p2 = capi.Params(nx=m, ny=m, nz=1, lattice=capi.LBM_D2Q9, s=[0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, sn, sn],
-                     visc_kind=capi.LBM_VISC_SMAGORINSKY, visc_strain=capi.LBM_STRAIN_YU,
-                     nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    w = _workloads()
+    p2 = w.params(w.load("C1"), lattice="D2Q9", grid={"nx": m, "ny": m, "nz": 1})
     s2 = lbm.LBM(p2, lbm.rho_u_field(np.zeros((1, m, m)), u2))
     log(f"D2Q9 {m}^2 LES")
     out["d2q9_les_4096sq"], _ = leg(torch, capi, s2, m * m, steps, warmup, 80)
@@ -427,9 +427,10 @@ def copy_bandwidth(torch, capi):
     return out
 
 
-def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50, visc="const"):
-    """Strain-squared loss gradient on the 128^3 recipe (seeded spectrum velocity, uniform
-    random force U(-1e-6, 1e-6), tau_nu = 0.8, 500 steps, checkpoint every 50): wall time of
+def adjoint_run(torch, np, synth, capi, lbm, warmup, visc="const"):
+    """Strain-squared loss gradient on the 128^3 workload (configs/c4_adjoint128.json: seeded
+    spectrum velocity, uniform random force U(-1e-6, 1e-6), tau_nu = 0.8, 500 steps,
+    checkpoint every 50): wall time of
     the forward pass and of the backward pass (recompute + adjoint); the same with every
     step's record kept by the forward sweep (no recompute; the gradient must come out with
     the same bits); and the adjoint kernel alone against HBM. Algorithmic bytes per node of the adjoint kernel: 200 for a constant
@@ -437,14 +438,20 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, n=128, nsteps=500, every=50
     C_s = 0.1 on top of nu0 = 0.1) 236 (+ 28 for the 7 extra record planes, + 8 for the
     s_nu-field adjoint in and out)."""
     from paper_1704_07559_amd import autograd as ag
+    w = _workloads()
+    cfg = w.load("C4")
+    n, nsteps, every = cfg["grid"]["nx"], cfg["steps"], cfg["checkpoint_every"]
     shape = (n, n, n)
     log(f"adjoint {n}^3 ({visc}): {nsteps} steps, checkpoint every {every}")
-    u0 = torch.as_tensor(synth.spectrum_velocity(shape, seed=1704, u_rms=0.04).astype(np.float32)).cuda()
-    F = torch.as_tensor(synth.uniform_random_force(shape, seed=7559, amp=1e-6).astype(np.float32)).cuda()
-    p = capi.Params(nx=n, ny=n, nz=n, s=rates(0.8))
+    ini, frc = cfg["init"], cfg["force"]
+    u0 = torch.as_tensor(synth.spectrum_velocity(shape, seed=ini["seed"], u_rms=ini["u_rms"], k0=ini["k0"])
+                         .astype(np.float32)).cuda()
+    F = torch.as_tensor(synth.uniform_random_force(shape, seed=frc["seed"], amp=frc["amplitude"])
+                        .astype(np.float32)).cuda()
+    p = w.params(cfg)
     bpn = 200
     if visc == "smagorinsky":
-        p.visc_kind, p.nu0, p.c_smag = capi.LBM_VISC_SMAGORINSKY, (0.8 - 0.5) / 3.0, 0.1
+        p.visc_kind, p.nu0, p.c_smag = capi.LBM_VISC_SMAGORINSKY, w.nu_of_tau(cfg["tau_nu"]), 0.1
         bpn = 236
     # warm-up on a short problem (kernel loading, allocator)
     u_w, F_w = u0.clone().requires_grad_(True), F.clone().requires_grad_(True)
@@ -645,8 +652,9 @@ def main():
         return
 
     n = args.n
+    ini = _workloads().load("C1")["init"]
     log(f"generating the {n}^3 initial field")
-    u = synth.spectrum_velocity((n, n, n), seed=1704, u_rms=0.04)
+    u = synth.spectrum_velocity((n, n, n), seed=ini["seed"], u_rms=ini["u_rms"], k0=ini["k0"])
     rho_u = lbm.rho_u_field(np.zeros((n, n, n)), u)
     sim = lbm.LBM(les_params(capi, n, capi.LBM_F32), rho_u)
     del rho_u
@@ -698,9 +706,10 @@ def main():
     if not args.no_extra:
         extra = {}
         K, W = args.steps, args.warmup
-        m = 384
+        cfg3 = _workloads().load("C3")
+        m, ini3 = cfg3["grid"]["nx"], cfg3["init"]
         log(f"generating the {m}^3 initial field")
-        u3 = synth.spectrum_velocity((m, m, m), seed=1704, u_rms=0.04)
+        u3 = synth.spectrum_velocity((m, m, m), seed=ini3["seed"], u_rms=ini3["u_rms"], k0=ini3["k0"])
         rho_u3 = lbm.rho_u_field(np.zeros((m, m, m)), u3)
         del u3
         for name, st, bpn in (("f16", capi.LBM_F16, 19 * 2 * 2 + 8), ("bf16", capi.LBM_BF16, 19 * 2 * 2 + 8),
@@ -740,9 +749,8 @@ def main():
         torch.cuda.empty_cache()
         # the same LES on the D3Q15 lattice (Yu-type formula of the Section 5.4 route):
         # 15 x 4 B read + written + 8 B lagged s_nu = 128 B/node
-        p15 = capi.Params(nx=n, ny=n, nz=n, lattice=capi.LBM_D3Q15, storage=capi.LBM_F32,
-                          s=rates15(0.51) + [0.0] * 4, visc_kind=capi.LBM_VISC_SMAGORINSKY,
-                          visc_strain=capi.LBM_STRAIN_YU, nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+        w = _workloads()
+        p15 = w.params(w.load("C1"), lattice="D3Q15", grid={"nx": n, "ny": n, "nz": n})
         s15 = lbm.LBM(p15, lbm.rho_u_field(np.zeros((n, n, n)), u))
         log(f"D3Q15 FP32 {n}^3 LES")
         extra["les256_d3q15"], _ = leg(torch, capi, s15, N, K, W, 128)

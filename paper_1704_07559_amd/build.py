@@ -59,6 +59,39 @@ def build(verbose: bool = False) -> Path:
     return LIB
 
 
+def build_sanitized(out: Path) -> Path:
+    """A copy of the library whose host C++ (the C ABI layer, capi.cpp) is built with the
+    address and undefined-behaviour sanitizers, linked with the device objects of the last
+    build(). For host-side checks on a machine without a GPU: load it with the sanitizer
+    runtime preloaded (``sanitizer_runtime()``) and ``LBM_LIBRARY`` pointing at it. Device code
+    is not instrumented."""
+    objs = [BUILD / (src.name + ".o") for src in sources() if src.suffix == ".hip"]
+    missing = [o for o in objs if not o.exists()]
+    if missing:
+        raise RuntimeError(f"run build() first: {missing[0]} is missing")
+    out = Path(out)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-fno-omit-frame-pointer", "-g"]
+    capi_obj = out.with_suffix(".capi.o")
+    cmd = [HIPCC, *COMMON, *san, "-c", str(CSRC / "capi.cpp"), "-o", str(capi_obj)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for capi.cpp (sanitized):\n{' '.join(cmd)}\n{r.stderr}")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan", *san[:4], "-o", str(out),
+           str(capi_obj), *map(str, objs)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed (sanitized):\n{' '.join(cmd)}\n{r.stderr}")
+    return out
+
+
+def sanitizer_runtime() -> str:
+    """Path of the compiler's shared address-sanitizer runtime (to preload into Python)."""
+    clang = Path(HIPCC).resolve().parent.parent / "llvm" / "bin" / "clang"
+    r = subprocess.run([str(clang), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
