@@ -136,7 +136,7 @@ def les_params(capi, n, storage):
     configs/c3_les384_half.json) on an n^3 box."""
     w = _workloads()
     name = {capi.LBM_F32: "f32", capi.LBM_F16: "f16", capi.LBM_BF16: "bf16"}[storage]
-    return w.params(w.load("C1"), storage=name, grid={"nx": n, "ny": n, "nz": n})
+    return w.params(w.load("C1" if name == "f32" else "C3"), storage=name, grid={"nx": n, "ny": n, "nz": n})
 
 
 def settle(torch, capi, seconds=0.25):
