@@ -433,7 +433,8 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, visc="const"):
     checkpoint every 50): wall time of
     the forward pass and of the backward pass (recompute + adjoint); the same with every
     step's record kept by the forward sweep (no recompute; the gradient must come out with
-    the same bits); and the adjoint kernel alone against HBM. Algorithmic bytes per node of the adjoint kernel: 200 for a constant
+    the same bits); and the adjoint kernel alone against HBM (per step of a multi-step sweep,
+    and as one step on canonical planes). Algorithmic bytes per node of the adjoint kernel: 200 for a constant
     viscosity (76 lambda in, 76 out, 12 j, 12 F, 24 grad_F); with visc="smagorinsky" (lagged,
     C_s = 0.1 on top of nu0 = 0.1) 236 (+ 28 for the 7 extra record planes, + 8 for the
     s_nu-field adjoint in and out)."""
@@ -480,25 +481,23 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, visc="const"):
     t5 = time.perf_counter()
     same = bool(Jr.item() == J.item() and torch.equal(u0.grad, gu_ck) and torch.equal(F.grad, gF_ck))
     torch.cuda.empty_cache()
-    # adjoint kernel alone
+    # adjoint kernel alone, as the backward sweep runs it: lbm_adjoint_steps over the record
+    # of K steps (the intermediate adjoint states row-interleaved), device time per step over
+    # at least a quarter second; and one lbm_adjoint_step on canonical planes
     N = n ** 3
     p.force_field = F.detach().reshape(3, N)
     sim = lbm.LBM(p)
-    jb = torch.zeros((1, sim.save_planes, N), device="cuda")
-    sim.step(1, save=jb)
+    K = 10
+    jb = torch.zeros((K, sim.save_planes, N), device="cuda")
+    sim.step(K, save=jb)
     la = torch.randn((sim.adjoint_planes, N), device="cuda")
     lb = torch.empty_like(la)
     gF = torch.zeros((3, N), device="cuda")
-    for _ in range(3):
-        capi.lbm_adjoint_step(sim.ctx, jb[0], la, lb, gF)
-    reps = 50
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        capi.lbm_adjoint_step(sim.ctx, jb[0], la, lb, gF)
-    e1.record()
-    torch.cuda.synchronize()
-    k_adj = e0.elapsed_time(e1) / 1e3 / reps
+    sweep = lambda: capi.lbm_adjoint_steps(sim.ctx, K, jb, la, lb, gF)
+    est = _event_time(torch, sweep, 3)
+    k_adj = _event_time(torch, sweep, max(5, math.ceil(0.25 / est))) / K
+    single = lambda: capi.lbm_adjoint_step(sim.ctx, jb[0], la, lb, gF)
+    k_one = _event_time(torch, single, max(50, math.ceil(0.25 / (est / K))))
     sim.close()
     fwd, bwd = t1 - t0, t2 - t1
     fwd_r, bwd_r = t4 - t3, t5 - t4
@@ -511,6 +510,7 @@ def adjoint_run(torch, np, synth, capi, lbm, warmup, visc="const"):
                          "same_gradient_bits": same},
             "adjoint_kernel_ms": round(k_adj * 1e3, 4), "adjoint_bytes_per_node": bpn,
             "adjoint_hbm_frac": round(bpn * N / k_adj / 1e9 / HBM_PEAK_GBS, 4),
+            "adjoint_single_step_ms": round(k_one * 1e3, 4),
             "grad_u0_norm": float(u0.grad.norm()), "grad_F_norm": float(F.grad.norm())}
 
 

@@ -244,7 +244,10 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const float* rec_n, const float* lam_i
  * record rec + n*R*N (R = lbm_save_planes(ctx), as one lbm_step(nsteps, ..., save) call
  * wrote them), the adjoint state ping-ponging between lam_a and lam_b (each device
  * float[lbm_adjoint_planes(ctx)*N], not overlapping). On entry lam_a holds the adjoint after
- * the last step; on return lam_a holds the adjoint before the first (lam_b is scratch).
+ * the last step; on return lam_a holds the adjoint before the first (lam_b is scratch: the
+ * states between the first and the last step are kept with planes 0..18 in the
+ * row-interleaved order of the population buffers, and its contents on return are
+ * unspecified). The result equals nsteps lbm_adjoint_step calls bit for bit.
  * grad_force as in lbm_adjoint_step. Saves a host round trip per step.
  */
 lbm_status lbm_adjoint_steps(lbm_ctx* ctx, int nsteps, const float* rec, float* lam_a, float* lam_b,

@@ -165,6 +165,13 @@ int adjoint_planes(const lbm_ctx* c) {
   return (c->V.kind == LBM_VISC_SMAGORINSKY || c->V.kind == LBM_VISC_POWERLAW) ? 20 : 19;
 }
 
+// Whether a multi-step reverse sweep keeps its intermediate adjoint states row-interleaved
+// (the per-lane byte offsets of a z-plane of 19 float runs must stay below 2^32; lbm_init
+// checks that bound for the storage type only, which may be 2 bytes).
+bool adjoint_rows(const lbm_ctx* c) {
+  return static_cast<size_t>(c->G.nx) * c->G.ny * 19 * sizeof(float) < (size_t(1) << 32);
+}
+
 }  // namespace
 
 extern "C" {
@@ -450,11 +457,12 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int nsteps, const float* rec, float* la
   }
   const hipStream_t s = as_stream(stream);
   const size_t rec_elems = static_cast<size_t>(save_planes(c->V)) * c->G.N;
+  const bool rows = adjoint_rows(c);
   float* in = lam_a;
   float* out = lam_b;
   for (int n = nsteps - 1; n >= 0; --n) {
     hipError_t e = d3q19::launch_adjoint_step(c->G, c->M, c->V, c->F, rec + static_cast<size_t>(n) * rec_elems, in,
-                                              out, grad_force, s);
+                                              out, grad_force, s, rows && n != nsteps - 1, rows && n != 0);
     if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps");
     float* t = in;
     in = out;
@@ -487,11 +495,12 @@ lbm_status lbm_adjoint_steps_noalloc(lbm_ctx* c, int nsteps, const float* rec, f
   hipError_t e = noalloc_scratch(s, &scratch);
   if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps_noalloc scratch lookup");
   const size_t rec_elems = static_cast<size_t>(save_planes(c->V)) * c->G.N;
+  const bool rows = adjoint_rows(c);
   float* in = lam;
   float* out = static_cast<float*>(scratch);
   for (int n = nsteps - 1; n >= 0; --n) {
     e = d3q19::launch_adjoint_step(c->G, c->M, c->V, c->F, rec + static_cast<size_t>(n) * rec_elems, in, out,
-                                   grad_force, s);
+                                   grad_force, s, rows && n != nsteps - 1, rows && n != 0);
     if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_steps_noalloc");
     float* t = in;
     in = out;

@@ -145,7 +145,12 @@ __device__ __forceinline__ StrainParts strain_parts(const float (&mn)[6], float 
 // the collision rate s_new depends on the state: the record of the forward step holds j,
 // m^neq of rows 1, 9, 11, 13, 14, 15 and the strain's rate s_x; for the lagged kinds plane 19
 // of lam_in / lam_out is the adjoint of the s_nu field (not streamed).
-template <bool VISC, bool STAGE>
+// IN_ROWS / OUT_ROWS: planes 0..18 of lam_in / lam_out in the row-interleaved order of the
+// population buffers (element (i, z, y, x) at ((z ny + y) 19 + i) nx + x) instead of the
+// canonical planes; a multi-step sweep keeps its intermediate states that way, so that
+// a wave's 38 adjoint streams fall into the DRAM pages of a few rows. Plane 19 stays a plane
+// (at 19 N) in both.
+template <bool VISC, bool STAGE, bool IN_ROWS, bool OUT_ROWS>
 __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, ViscF V, ForceF Fo,
                                                             const float* __restrict__ rec,
                                                             const float* __restrict__ lam_in,
@@ -159,10 +164,17 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, Vis
   const unsigned self = ne.self;
   const Nbr nb = in_bytes<float>(ne);
   const size_t N = G.N;
+  Rows<Q, float> rows;
+  if constexpr (IN_ROWS || OUT_ROWS) rows = rows_of<Q, float>(G, x, y, z);
 
   float lt[Q];
-  if constexpr (STAGE) pull_staged<LatRev, float, true>(lam_in, G, nb, y, lt);
-  else pull<LatRev, float>(lam_in, G, nb, y, lt);
+  if constexpr (IN_ROWS) {
+    if constexpr (STAGE) pull_rows_staged<LatRev, float, true>(lam_in, G, rows, y, lt);
+    else pull_rows<LatRev, float>(lam_in, G, rows, y, lt);
+  } else {
+    if constexpr (STAGE) pull_staged<LatRev, float, true>(lam_in, G, nb, y, lt);
+    else pull<LatRev, float>(lam_in, G, nb, y, lt);
+  }
 
   // mu = D^-1 T lam~
   const Pairs P = make_pairs(lt);
@@ -276,7 +288,8 @@ __global__ __launch_bounds__(kMaxBlock) void adjoint_kernel(Geo G, ModelF M, Vis
 
   float lo[Q];
   apply_transpose(nu, lo);
-  store_local<Q>(lam_out, G, nb.self, lo);
+  if constexpr (OUT_ROWS) store_rows<Q, float>(lam_out, G, rows, lo);
+  else store_local<Q>(lam_out, G, nb.self, lo);
 
   if (grad_force) {
     // G(j) = d S_F / d F
@@ -421,19 +434,40 @@ __global__ __launch_bounds__(kMaxBlock) void init_adjoint_kernel(Geo G, ModelF M
   grad_u0[2 * N + self] = M.rho0 * (gz - 3.0f * uz * sl);
 }
 
-hipError_t launch_adjoint_step(const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const float* rec,
-                               const float* lam_in, float* lam_out, float* grad_force, hipStream_t st) {
+template <bool IN_ROWS, bool OUT_ROWS>
+static hipError_t launch_adjoint_layout(const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo,
+                                        const float* rec, const float* lam_in, float* lam_out, float* grad_force,
+                                        hipStream_t st) {
   const Launch L = node_launch(G);
   // whole-row blocks exchange the x-shifted adjoint elements through LDS (pull_mode 2)
   const bool stage = pull_mode(G, L.block) == 2;
   if (V.kind == 0) {
-    if (stage) hipLaunchKernelGGL((adjoint_kernel<false, true>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
-    else hipLaunchKernelGGL((adjoint_kernel<false, false>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+    if (stage)
+      hipLaunchKernelGGL((adjoint_kernel<false, true, IN_ROWS, OUT_ROWS>), L.grid, L.block, 0, st, G, M, V, Fo, rec,
+                         lam_in, lam_out, grad_force);
+    else
+      hipLaunchKernelGGL((adjoint_kernel<false, false, IN_ROWS, OUT_ROWS>), L.grid, L.block, 0, st, G, M, V, Fo, rec,
+                         lam_in, lam_out, grad_force);
   } else {
-    if (stage) hipLaunchKernelGGL((adjoint_kernel<true, true>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
-    else hipLaunchKernelGGL((adjoint_kernel<true, false>), L.grid, L.block, 0, st, G, M, V, Fo, rec, lam_in, lam_out, grad_force);
+    if (stage)
+      hipLaunchKernelGGL((adjoint_kernel<true, true, IN_ROWS, OUT_ROWS>), L.grid, L.block, 0, st, G, M, V, Fo, rec,
+                         lam_in, lam_out, grad_force);
+    else
+      hipLaunchKernelGGL((adjoint_kernel<true, false, IN_ROWS, OUT_ROWS>), L.grid, L.block, 0, st, G, M, V, Fo, rec,
+                         lam_in, lam_out, grad_force);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const float* rec,
+                               const float* lam_in, float* lam_out, float* grad_force, hipStream_t st, bool in_rows,
+                               bool out_rows) {
+  if (in_rows) {
+    if (out_rows) return launch_adjoint_layout<true, true>(G, M, V, Fo, rec, lam_in, lam_out, grad_force, st);
+    return launch_adjoint_layout<true, false>(G, M, V, Fo, rec, lam_in, lam_out, grad_force, st);
+  }
+  if (out_rows) return launch_adjoint_layout<false, true>(G, M, V, Fo, rec, lam_in, lam_out, grad_force, st);
+  return launch_adjoint_layout<false, false>(G, M, V, Fo, rec, lam_in, lam_out, grad_force, st);
 }
 
 hipError_t launch_loss_seed(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo,

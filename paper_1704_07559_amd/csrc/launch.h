@@ -23,8 +23,11 @@ hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hi
 hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
 hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
                          const float* snu, double* partials, double* out, hipStream_t);
+// in_rows / out_rows: planes 0..18 of lam_in / lam_out row-interleaved (as the population
+// buffers) instead of canonical planes; a multi-step sweep keeps its intermediate states so.
 hipError_t launch_adjoint_step(const Geo&, const ModelF&, const ViscF&, const ForceF&, const float* rec,
-                               const float* lam_in, float* lam_out, float* grad_force, hipStream_t);
+                               const float* lam_in, float* lam_out, float* grad_force, hipStream_t,
+                               bool in_rows = false, bool out_rows = false);
 hipError_t launch_loss_seed(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
                             const float* snu, float* lam_out, float* grad_force, double* partials, double* out,
                             hipStream_t);

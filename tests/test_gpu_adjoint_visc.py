@@ -142,16 +142,25 @@ def test_record_planes_and_validation():
     sim2.close()
 
 
-@pytest.mark.parametrize("name,nsteps", [("const", 5), ("const", 4), ("smag_yu", 3), ("implicit_chai", 6)])
-def test_adjoint_steps_equals_single_steps(name, nsteps):
-    """lbm_adjoint_steps (one call, lambda ping-pong inside the library) is bit-identical to
-    nsteps lbm_adjoint_step calls, for odd and even nsteps; the result lands in lam_a."""
+# (model, nsteps, (nz, ny, nx), walls): whole rows with masked lanes (ny not a multiple of the
+# block's rows, or nx not a power of two), whole rows through LDS, part rows (nx = 512), with
+# and without y-walls; nsteps 1 and 2 have no intermediate (row-interleaved) state or one.
+SWEEPS = [("const", 5, (4, 9, 64), False), ("const", 4, (4, 8, 64), False), ("const", 1, (4, 8, 64), True),
+          ("smag_yu", 3, (4, 9, 64), False), ("smag_yu", 3, (2, 4, 512), True), ("smag_chai", 2, (4, 8, 64), True),
+          ("implicit_chai", 6, (4, 9, 64), False), ("implicit_yu", 4, (4, 8, 64), True),
+          ("powerlaw_thinning", 5, (3, 5, 96), False)]
+
+
+@pytest.mark.parametrize("name,nsteps,shape,walls", SWEEPS)
+def test_adjoint_steps_equals_single_steps(name, nsteps, shape, walls):
+    """lbm_adjoint_steps (one call, lambda ping-pong inside the library, the intermediate
+    states row-interleaved) is bit-identical to nsteps lbm_adjoint_step calls on canonical
+    planes, for odd and even nsteps and every launch shape; the result lands in lam_a."""
     import torch
     from paper_1704_07559_amd import capi, lbm
-    shape = (4, 9, 64)
     F = _f32(synth.uniform_random_force(shape, seed=60, amp=1e-4))
     kw = {} if name == "const" else MODELS[name]
-    op, cp, _ = spec_params(shape, tau=0.8, force=F, **kw)
+    op, cp, _ = spec_params(shape, tau=0.8, walls=walls, force=F, **kw)
     u = synth.random_vector(shape, seed=61, scale=0.05)
     sim = lbm.LBM(cp, lbm.rho_u_field(np.zeros(shape), u))
     N, R, A = cp.N, sim.save_planes, sim.adjoint_planes
