@@ -25,8 +25,11 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
+// kMixedFma: the arithmetic may take loaded values straight into mixed-precision FMAs
+// (v_fma_mix_f32 reads FP16 operands; there is no such form for BF16).
 template <>
 struct Codec<float> {
+  static constexpr bool kMixedFma = false;
   static __device__ __forceinline__ float load_cached(const float* p) { return *p; }
   static __device__ __forceinline__ float load(const float* p) { return stream_load(p); }
   static __device__ __forceinline__ void store(float* p, float v) { stream_store(p, v); }
@@ -34,6 +37,7 @@ struct Codec<float> {
 
 template <>
 struct Codec<_Float16> {
+  static constexpr bool kMixedFma = true;
   static __device__ __forceinline__ float load_cached(const _Float16* p) { return static_cast<float>(*p); }
   static __device__ __forceinline__ float load(const _Float16* p) { return static_cast<float>(stream_load(p)); }
   // fptrunc float -> half rounds to nearest even (default rounding mode).
@@ -47,6 +51,7 @@ struct Codec<_Float16> {
 
 template <>
 struct Codec<__bf16> {
+  static constexpr bool kMixedFma = false;
   static __device__ __forceinline__ float load_cached(const __bf16* p) { return static_cast<float>(*p); }
   static __device__ __forceinline__ float load(const __bf16* p) { return static_cast<float>(stream_load(p)); }
   // fptrunc float -> bfloat rounds to nearest even.

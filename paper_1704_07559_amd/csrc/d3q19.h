@@ -149,6 +149,36 @@ __device__ __forceinline__ Pairs make_pairs(const float (&g)[Q]) {
   return P;
 }
 
+// A 1.0 the compiler cannot fold (an empty asm claims to change it; it lives in a scalar
+// register). Written as fma(h, one, x), the sum of a population loaded from FP16 storage and
+// an FP32 value becomes one mixed-precision FMA that reads the FP16 operand directly
+// (v_fma_mix_f32), where h + x would first convert h (a plain add is not fused with the
+// conversion). The result is the same rounded sum.
+__device__ __forceinline__ float opaque_one() {
+  float one = 1.0f;
+  asm("" : "+s"(one));
+  return one;
+}
+
+// make_pairs with the sums and differences written as such FMAs (MIX), for populations
+// converted from FP16 on load: none of the 19 conversions is then issued on its own.
+template <bool MIX>
+__device__ __forceinline__ Pairs make_pairs_for(const float (&g)[Q]) {
+  if constexpr (!MIX) {
+    return make_pairs(g);
+  } else {
+    const float one = opaque_one();
+    Pairs P;
+    P.g0 = g[0];
+    static_for<NP>([&](auto pi) {
+      constexpr int p = pi;
+      P.s[p] = __builtin_fmaf(g[DV.pa[p]], one, g[DV.pb[p]]);
+      P.d[p] = __builtin_fmaf(g[DV.pb[p]], -one, g[DV.pa[p]]);
+    });
+    return P;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Factored transforms. The rows of T share partial sums of the pair sums and differences:
 // the density, e and eps rows see only g_0, the sum over the six axis directions and the
@@ -412,15 +442,35 @@ __device__ __forceinline__ void force_moments(float jx, float jy, float jz, floa
 
 // g += T^T w for rows 1..18 (w[0] is not read: the density row is conserved by every
 // collision and every initial non-equilibrium part).
+template <bool MIX = false>
 __device__ __forceinline__ void add_scaled_back_transform(const float (&w)[Q], float (&g)[Q]) {
   float dg0, e[NP], o[NP];
   back_transform<float>(w, dg0, e, o);
-  g[0] += dg0;
-  static_for<NP>([&](auto pi) {
-    constexpr int p = pi;
-    g[DV.pa[p]] += e[p] + o[p];
-    g[DV.pb[p]] += e[p] - o[p];
-  });
+  if constexpr (!MIX) {
+    g[0] += dg0;
+    static_for<NP>([&](auto pi) {
+      constexpr int p = pi;
+      g[DV.pa[p]] += e[p] + o[p];
+      g[DV.pb[p]] += e[p] - o[p];
+    });
+  } else {
+    // the same sums as mixed-precision FMAs (make_pairs_for). g holds FP16 values here, so
+    // the round trip through _Float16 is exact; the empty asm makes each a fresh value at
+    // this point, so that its conversion is not shared with (and hoisted to) the first use
+    // and can join the FMA.
+    const float one = opaque_one();
+    auto fresh = [](float v) {
+      _Float16 h = static_cast<_Float16>(v);
+      asm("" : "+v"(h));
+      return static_cast<float>(h);
+    };
+    g[0] = __builtin_fmaf(fresh(g[0]), one, dg0);
+    static_for<NP>([&](auto pi) {
+      constexpr int p = pi;
+      g[DV.pa[p]] = __builtin_fmaf(fresh(g[DV.pa[p]]), one, e[p] + o[p]);
+      g[DV.pb[p]] = __builtin_fmaf(fresh(g[DV.pb[p]]), one, e[p] - o[p]);
+    });
+  }
 }
 
 // g += T^-1 dm = T^T (D^-1 dm) for rows 1..18 (dm[0] is not read).

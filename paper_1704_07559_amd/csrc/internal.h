@@ -336,7 +336,14 @@ __device__ __forceinline__ void store_rows(S* __restrict__ dst, const Geo& G, co
       stream_store(reinterpret_cast<unsigned short*>(cb + i * run + self), static_cast<unsigned short>(w & 0xffffu));
       stream_store(reinterpret_cast<unsigned short*>(cb + (i + 1) * run + self), static_cast<unsigned short>(w >> 16));
     });
-    if constexpr (Q % 2 != 0) store_at<S>(cb + (Q - 1) * run, self, g[Q - 1]);
+    if constexpr (Q % 2 != 0) {
+      // the odd population alone: its FP32 value is rounded to 16 bits as it is. (An FMA
+      // producing it from FP16 operands would otherwise be fused with the rounding into one
+      // v_fma_mixlo_f16, rounding the exact result once instead of the FP32 result.)
+      float last = g[Q - 1];
+      if constexpr (Codec<S>::kMixedFma) asm("" : "+v"(last));
+      store_at<S>(cb + (Q - 1) * run, self, last);
+    }
   } else {
     static_for<Q>([&](auto ii) {
       constexpr int i = ii;

@@ -21,11 +21,12 @@ namespace d3q19 {
 // state (Yu and/or Chai, with the lagged s_nu or the implicitly solved one), viscosity
 // model, relaxation with the Guo term, back-transform. g holds the pulled pre-collision
 // populations on entry and the post-collision populations on exit; `self` is the node's
-// element offset in the fields.
-template <bool CORR>
+// element offset in the fields. MIX: g was converted from FP16 on load, and its two uses
+// (pair sums, final sum) take the FP16 values directly (make_pairs_for).
+template <bool CORR, bool MIX>
 __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const Geo& G, const ModelF& M,
                                             const ViscF& V, const ForceF& Fo, const StepIO& io) {
-  const Pairs P_ = make_pairs(g);
+  const Pairs P_ = make_pairs_for<MIX>(g);
   const float drho = delta_rho(P_);
   float jx = momentum<0>(P_), jy = momentum<1>(P_), jz = momentum<2>(P_);
   float Fx, Fy, Fz;
@@ -113,7 +114,7 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
       }
     });
   }
-  add_scaled_back_transform(w, g);
+  add_scaled_back_transform<MIX>(w, g);
 
   if (io.save) {
     // what the adjoint of this step needs: j, and for a strain-dependent viscosity the
@@ -150,7 +151,9 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   float g[Q];
   if constexpr (XMODE == 2) pull_rows_staged<Lat, S, WALLS>(static_cast<const S*>(io.src), G, r, y, g);
   else pull_rows<Lat, S, WALLS, XMODE == 1>(static_cast<const S*>(io.src), G, r, y, g);
-  node_update<CORR>(g, node_index(G, x, y, z), G, M, V, Fo, io);
+  // the FP16 values go straight into mixed-precision FMAs, except with the LDS exchange,
+  // whose x-shifted populations arrive converted
+  node_update<CORR, Codec<S>::kMixedFma && XMODE != 2>(g, node_index(G, x, y, z), G, M, V, Fo, io);
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
