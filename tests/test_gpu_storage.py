@@ -191,8 +191,10 @@ STEP_CASES = {
 }
 
 # every way a block pulls along x: whole rows with masked lanes (nx = 69), whole rows through
-# LDS (nx = 128 with two rows per block, 256), part rows (384)
-STEP_SHAPES = [(4, 10, 69), (3, 8, 128), (2, 5, 256), (2, 4, 384)]
+# LDS (nx = 128 with two rows per block, 256), part rows (384). The part-row box holds 24576
+# nodes: rounding an FMA's exact result once to 16 bits (a fused mixed-precision FMA) instead
+# of its FP32 result differs about once in 2^13 roundings, so three steps there would show it.
+STEP_SHAPES = [(4, 10, 69), (3, 8, 128), (2, 5, 256), (8, 8, 384)]
 
 
 @pytest.mark.parametrize("shape", STEP_SHAPES)
