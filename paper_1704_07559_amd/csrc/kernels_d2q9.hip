@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ViscF V, F
       acc[4] += jj * (0.5 / M.rho0);
       acc[5] += static_cast<double>(S3[0]) * S3[0] + static_cast<double>(S3[1]) * S3[1] +
                 2.0 * static_cast<double>(S3[2]) * S3[2];
-      acc[6] = fmax(acc[6], sqrt(jj) / M.rho0);
+      acc[6] = fmax(acc[6], jj);  // max |j|^2: the final pass takes sqrt(.) / rho0 once
       acc[7] += bad;
     }
   }
@@ -420,7 +420,7 @@ hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ViscF
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_final(partials, static_cast<int>(nb), out, st);
+  return launch_reduce_final(partials, static_cast<int>(nb), out, st, static_cast<double>(M.rho0));
 }
 
 }  // namespace d2q9

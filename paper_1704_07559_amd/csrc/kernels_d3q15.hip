@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ViscF V, F
                 static_cast<double>(S6[2]) * S6[2] +
                 2.0 * (static_cast<double>(S6[3]) * S6[3] + static_cast<double>(S6[4]) * S6[4] +
                        static_cast<double>(S6[5]) * S6[5]);
-      acc[6] = fmax(acc[6], sqrt(jj) / M.rho0);
+      acc[6] = fmax(acc[6], jj);  // max |j|^2: the final pass takes sqrt(.) / rho0 once
       acc[7] += bad;
     }
   }
@@ -445,7 +445,7 @@ hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ViscF
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_final(partials, static_cast<int>(nb), out, st);
+  return launch_reduce_final(partials, static_cast<int>(nb), out, st, static_cast<double>(M.rho0));
 }
 
 }  // namespace d3q15

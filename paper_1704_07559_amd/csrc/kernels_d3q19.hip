@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(Geo G, ModelF M, ViscF V, F
 #pragma unroll
       for (int c = 0; c < 6; ++c) ss += (c < 3 ? 1.0 : 2.0) * static_cast<double>(S6[c]) * S6[c];
       acc[5] += ss;
-      acc[6] = fmax(acc[6], sqrt(jj) / M.rho0);
+      acc[6] = fmax(acc[6], jj);  // max |j|^2: the final pass takes sqrt(.) / rho0 once
       acc[7] += bad;
     }
   }
@@ -232,7 +232,7 @@ hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ViscF
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce_final(partials, static_cast<int>(nb), out, st);
+  return launch_reduce_final(partials, static_cast<int>(nb), out, st, static_cast<double>(M.rho0));
 }
 
 }  // namespace d3q19

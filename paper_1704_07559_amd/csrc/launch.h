@@ -9,7 +9,7 @@ namespace lbm {
 
 // Reductions: 8 doubles per block (at most kReduceBlocks blocks, each taking whole x-rows),
 // then one block folds the partials in a fixed order.
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 4096;
 constexpr int kReduceVals = 8;
 
 namespace d3q19 {
@@ -69,7 +69,9 @@ constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 // no allocation).
 hipError_t noalloc_scratch(hipStream_t stream, void** out);
 
-hipError_t launch_reduce_final(const double* partials, int nblocks, double* out, hipStream_t);
+// Fold nblocks partials into out[0..7]. rho0 > 0 (the diagnostics): slot 6 arrives as the
+// largest |j|^2 and leaves as max |u| = sqrt(.) / rho0.
+hipError_t launch_reduce_final(const double* partials, int nblocks, double* out, hipStream_t, double rho0 = 0.0);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t);
 
 }  // namespace lbm
