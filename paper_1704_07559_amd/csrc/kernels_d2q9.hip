@@ -121,7 +121,6 @@ template <typename S, bool WALLS, int XMODE, bool CORR>
 __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
   if (x >= G.nx || y >= G.ny) return;
   const unsigned self = node_index(G, x, y, 0);
   const Rows<Q, S> r = rows_of<Q, S>(G, x, y, 0);
