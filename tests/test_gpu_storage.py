@@ -36,8 +36,9 @@ def _record(name, data):
             json.dump(data, f, indent=1)
 
 
-def test_storage_error_against_fp64_oracle_64_cubed():
-    import torch
+def _storage_errors_64(steps):
+    """FP32, FP16 and BF16 runs of the 64^3 LES field against the FP64 oracle at each step of
+    `steps`: populations, Yu strain and kinetic energy, relative."""
     from paper_1704_07559_amd import capi, lbm
     n = 64
     shape = (n, n, n)
@@ -46,7 +47,7 @@ def test_storage_error_against_fp64_oracle_64_cubed():
     op, _, _ = spec_params(shape, **LES)
     ref = od.Simulation(op, od.init_populations(dr, u, op))
     refs = {}
-    for n_target in (10, 100):
+    for n_target in steps:
         ref.step(n_target - ref.n)
         refs[n_target] = (ref.g.copy(), ref.strain("yu"), ref.diagnostics()["ke"])
     out = {}
@@ -54,7 +55,7 @@ def test_storage_error_against_fp64_oracle_64_cubed():
         _, cp, _ = spec_params(shape, storage=storage, **LES)
         sim = lbm.LBM(cp, lbm.rho_u_field(dr, u))
         done = 0
-        for n_target in (10, 100):
+        for n_target in steps:
             sim.step(n_target - done)
             done = n_target
             g_ref, S_ref, ke_ref = refs[n_target]
@@ -64,14 +65,36 @@ def test_storage_error_against_fp64_oracle_64_cubed():
                 "ke_rel": abs(sim.reduce()["ke"] - ke_ref) / ke_ref,
             }
         sim.close()
-    _record("storage_errors_64.json", out)
-    assert out["f32_step100"]["pop_rel"] < 1e-5 and out["f32_step100"]["strain_rel"] < 1e-4, out
+    return out
+
+
+def _check_storage_errors(out, steps):
+    last = steps[-1]
+    assert out[f"f32_step{last}"]["pop_rel"] < 1e-5 and out[f"f32_step{last}"]["strain_rel"] < 1e-4, out
     for st, eps in (("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
-        for n_target in (10, 100):
+        for n_target in steps:
             e = out[f"{st}_step{n_target}"]
             assert e["pop_rel"] < 20 * eps * np.sqrt(n_target), (st, n_target, e)
             assert e["ke_rel"] < 200 * eps, (st, n_target, e)
             assert np.isfinite(e["strain_rel"])
+
+
+def test_storage_error_against_fp64_oracle_64_cubed():
+    steps = (10, 100)
+    out = _storage_errors_64(steps)
+    _record("storage_errors_64.json", out)
+    _check_storage_errors(out, steps)
+
+
+@pytest.mark.skipif(not os.environ.get("LBM_LONG_ORACLE"),
+                    reason="the FP64 oracle takes about two minutes of host time for 1000 steps at 64^3; "
+                           "set LBM_LONG_ORACLE=1 to run it")
+def test_storage_error_against_fp64_oracle_64_cubed_1000_steps():
+    """The same comparison carried to step 1000 (the run length of the 384^3 workload)."""
+    steps = (10, 100, 1000)
+    out = _storage_errors_64(steps)
+    _record("storage_errors_64_1000.json", out)
+    _check_storage_errors(out, steps)
 
 
 @pytest.mark.slow
