@@ -160,23 +160,43 @@ __device__ __forceinline__ float opaque_one() {
   return one;
 }
 
-// make_pairs with the sums and differences written as such FMAs (MIX), for populations
-// converted from FP16 on load: none of the 19 conversions is then issued on its own.
-template <bool MIX>
-__device__ __forceinline__ Pairs make_pairs_for(const float (&g)[Q]) {
-  if constexpr (!MIX) {
-    return make_pairs(g);
-  } else {
-    const float one = opaque_one();
-    Pairs P;
-    P.g0 = g[0];
-    static_for<NP>([&](auto pi) {
-      constexpr int p = pi;
-      P.s[p] = __builtin_fmaf(g[DV.pa[p]], one, g[DV.pb[p]]);
-      P.d[p] = __builtin_fmaf(g[DV.pb[p]], -one, g[DV.pa[p]]);
-    });
-    return P;
-  }
+// Populations loaded from FP16 storage, kept two per register (pair order DV.pa / DV.pb) from
+// the pull to the final sums: 10 registers instead of 19 live across the node update, which
+// lets the FP16 step run 6 waves per SIMD instead of 5. The empty asm makes each packed pair
+// opaque at the two places it is read, so that it is neither unpacked nor converted early
+// (a conversion shared by the first and the last use would keep 19 FP32 values live again).
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+struct HalfPairs {
+  h16x2 v[NP];
+  _Float16 h0;
+};
+
+// g: the pulled populations, each converted from FP16 (so the narrowing here is exact).
+__device__ __forceinline__ HalfPairs pack_pairs(const float (&g)[Q]) {
+  HalfPairs hp;
+  hp.h0 = static_cast<_Float16>(g[0]);
+  asm("" : "+v"(hp.h0));
+  static_for<NP>([&](auto pi) {
+    constexpr int p = pi;
+    hp.v[p] = (h16x2){static_cast<_Float16>(g[DV.pa[p]]), static_cast<_Float16>(g[DV.pb[p]])};
+    asm("" : "+v"(hp.v[p]));
+  });
+  return hp;
+}
+
+// make_pairs from the packed values: each sum and difference one mixed-precision FMA that
+// reads its two FP16 operands from the halves of one register.
+__device__ __forceinline__ Pairs make_pairs_packed(const HalfPairs& hp) {
+  const float one = opaque_one();
+  Pairs P;
+  P.g0 = static_cast<float>(hp.h0);
+  static_for<NP>([&](auto pi) {
+    constexpr int p = pi;
+    const float a = static_cast<float>(hp.v[p].x), b = static_cast<float>(hp.v[p].y);
+    P.s[p] = __builtin_fmaf(a, one, b);
+    P.d[p] = __builtin_fmaf(b, -one, a);
+  });
+  return P;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -442,35 +462,34 @@ __device__ __forceinline__ void force_moments(float jx, float jy, float jz, floa
 
 // g += T^T w for rows 1..18 (w[0] is not read: the density row is conserved by every
 // collision and every initial non-equilibrium part).
-template <bool MIX = false>
 __device__ __forceinline__ void add_scaled_back_transform(const float (&w)[Q], float (&g)[Q]) {
   float dg0, e[NP], o[NP];
   back_transform<float>(w, dg0, e, o);
-  if constexpr (!MIX) {
-    g[0] += dg0;
-    static_for<NP>([&](auto pi) {
-      constexpr int p = pi;
-      g[DV.pa[p]] += e[p] + o[p];
-      g[DV.pb[p]] += e[p] - o[p];
-    });
-  } else {
-    // the same sums as mixed-precision FMAs (make_pairs_for). g holds FP16 values here, so
-    // the round trip through _Float16 is exact; the empty asm makes each a fresh value at
-    // this point, so that its conversion is not shared with (and hoisted to) the first use
-    // and can join the FMA.
-    const float one = opaque_one();
-    auto fresh = [](float v) {
-      _Float16 h = static_cast<_Float16>(v);
-      asm("" : "+v"(h));
-      return static_cast<float>(h);
-    };
-    g[0] = __builtin_fmaf(fresh(g[0]), one, dg0);
-    static_for<NP>([&](auto pi) {
-      constexpr int p = pi;
-      g[DV.pa[p]] = __builtin_fmaf(fresh(g[DV.pa[p]]), one, e[p] + o[p]);
-      g[DV.pb[p]] = __builtin_fmaf(fresh(g[DV.pb[p]]), one, e[p] - o[p]);
-    });
-  }
+  g[0] += dg0;
+  static_for<NP>([&](auto pi) {
+    constexpr int p = pi;
+    g[DV.pa[p]] += e[p] + o[p];
+    g[DV.pb[p]] += e[p] - o[p];
+  });
+}
+
+// The same sums from the packed FP16 pre-collision populations, g = hp + T^T w, as
+// mixed-precision FMAs (the same rounded sums as above).
+__device__ __forceinline__ void add_scaled_back_transform_packed(const float (&w)[Q], const HalfPairs& hp,
+                                                                 float (&g)[Q]) {
+  float dg0, e[NP], o[NP];
+  back_transform<float>(w, dg0, e, o);
+  const float one = opaque_one();
+  _Float16 h0 = hp.h0;
+  asm("" : "+v"(h0));
+  g[0] = __builtin_fmaf(static_cast<float>(h0), one, dg0);
+  static_for<NP>([&](auto pi) {
+    constexpr int p = pi;
+    h16x2 v = hp.v[p];
+    asm("" : "+v"(v));
+    g[DV.pa[p]] = __builtin_fmaf(static_cast<float>(v.x), one, e[p] + o[p]);
+    g[DV.pb[p]] = __builtin_fmaf(static_cast<float>(v.y), one, e[p] - o[p]);
+  });
 }
 
 // g += T^-1 dm = T^T (D^-1 dm) for rows 1..18 (dm[0] is not read).

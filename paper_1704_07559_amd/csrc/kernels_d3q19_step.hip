@@ -21,12 +21,20 @@ namespace d3q19 {
 // state (Yu and/or Chai, with the lagged s_nu or the implicitly solved one), viscosity
 // model, relaxation with the Guo term, back-transform. g holds the pulled pre-collision
 // populations on entry and the post-collision populations on exit; `self` is the node's
-// element offset in the fields. MIX: g was converted from FP16 on load, and its two uses
-// (pair sums, final sum) take the FP16 values directly (make_pairs_for).
-template <bool CORR, bool MIX>
+// element offset in the fields. PACK: g was converted from FP16 on load; the FP16 values are
+// kept packed (pack_pairs) and both their uses, the pair sums and the final sums, read them
+// through mixed-precision FMAs.
+template <bool CORR, bool PACK>
 __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const Geo& G, const ModelF& M,
                                             const ViscF& V, const ForceF& Fo, const StepIO& io) {
-  const Pairs P_ = make_pairs_for<MIX>(g);
+  HalfPairs hp;
+  Pairs P_;
+  if constexpr (PACK) {
+    hp = pack_pairs(g);
+    P_ = make_pairs_packed(hp);
+  } else {
+    P_ = make_pairs(g);
+  }
   const float drho = delta_rho(P_);
   float jx = momentum<0>(P_), jy = momentum<1>(P_), jz = momentum<2>(P_);
   float Fx, Fy, Fz;
@@ -114,7 +122,8 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
       }
     });
   }
-  add_scaled_back_transform<MIX>(w, g);
+  if constexpr (PACK) add_scaled_back_transform_packed(w, hp, g);
+  else add_scaled_back_transform(w, g);
 
   if (io.save) {
     // what the adjoint of this step needs: j, and for a strain-dependent viscosity the
@@ -141,8 +150,18 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
 // XMODE: how a block pulls along x (pull_mode: 0 part rows, 1 whole rows, 2 whole rows with
 // the LDS exchange). CORR: the force-corrected strain (a separate instance, so that the plain
 // step keeps its register budget).
+// FP16 storage without the LDS exchange (whose x-shifted values arrive through LDS as FP32)
+// keeps the pulled values packed; that instance fits 80 VGPRs without spilling and is asked
+// for 6 waves per SIMD (the 16-bit step moves half the bytes per wave, so it needs the extra
+// wave in flight: 4 instead of 5 waves cost it 6.5 %, 6 instead of 5 gained 3.7 %).
+template <typename S, int XMODE, bool CORR>
+constexpr bool kPackHalves = Codec<S>::kMixedFma && XMODE != 2;
+template <typename S, int XMODE, bool CORR>
+constexpr int kMinWavesPerEU = (kPackHalves<S, XMODE, CORR> && !CORR) ? 6 : 1;
+
 template <typename S, bool WALLS, int XMODE, bool CORR>
-__global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+__global__ __launch_bounds__(kMaxBlock, (kMinWavesPerEU<S, XMODE, CORR>)) void step_kernel(Geo G, ModelF M, ViscF V,
+                                                                                       ForceF Fo, StepIO io) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -151,9 +170,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   float g[Q];
   if constexpr (XMODE == 2) pull_rows_staged<Lat, S, WALLS>(static_cast<const S*>(io.src), G, r, y, g);
   else pull_rows<Lat, S, WALLS, XMODE == 1>(static_cast<const S*>(io.src), G, r, y, g);
-  // the FP16 values go straight into mixed-precision FMAs, except with the LDS exchange,
-  // whose x-shifted populations arrive converted
-  node_update<CORR, Codec<S>::kMixedFma && XMODE != 2>(g, node_index(G, x, y, z), G, M, V, Fo, io);
+  node_update<CORR, kPackHalves<S, XMODE, CORR>>(g, node_index(G, x, y, z), G, M, V, Fo, io);
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
