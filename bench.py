@@ -580,6 +580,10 @@ def main():
                          "order (counter collection)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="only run three 6-step adjoint sweeps (lbm_adjoint_steps) on an --n^3 box, constant "
+                         "viscosity then lagged Smagorinsky, after the forward steps that record them "
+                         "(counter collection)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -622,6 +626,40 @@ def main():
         sim.close()
         print(json.dumps({"probe": "slab" if args.slab_probe else args.storage_probe,
                           "steps": args.warmup + args.steps, "nonfinite": d["nonfinite"]}))
+        return
+
+    if args.adjoint_probe:
+        # the C4 recipe (seeded spectrum velocity, uniform random force field, tau_nu = 0.8) on
+        # an n^3 box; the sweep's first step reads canonical planes and writes row-interleaved
+        # states, its last reads them and writes canonical planes, the 4 between stay
+        # row-interleaved
+        w = _workloads()
+        cfg = w.load("C4")
+        n, K = args.n, 6
+        N = n ** 3
+        ini, frc = cfg["init"], cfg["force"]
+        u = synth.spectrum_velocity((n, n, n), seed=ini["seed"], u_rms=ini["u_rms"], k0=ini["k0"])
+        F = torch.as_tensor(synth.uniform_random_force((n, n, n), seed=frc["seed"], amp=frc["amplitude"])
+                            .astype(np.float32)).cuda().reshape(3, N)
+        for visc in ("const", "smagorinsky"):
+            p = w.params(cfg, grid={"nx": n, "ny": n, "nz": n})
+            if visc == "smagorinsky":
+                p.visc_kind, p.nu0, p.c_smag = capi.LBM_VISC_SMAGORINSKY, w.nu_of_tau(cfg["tau_nu"]), 0.1
+            p.force_field = F
+            sim = lbm.LBM(p, lbm.rho_u_field(np.zeros((n, n, n)), u))
+            rec = torch.empty((K, sim.save_planes, N), device="cuda")
+            sim.step(K, save=rec)
+            la = torch.randn((sim.adjoint_planes, N), device="cuda")
+            lb = torch.empty_like(la)
+            gF = torch.zeros((3, N), device="cuda")
+            settle(torch, capi)
+            for _ in range(3):
+                capi.lbm_adjoint_steps(sim.ctx, K, rec, la, lb, gF)
+            torch.cuda.synchronize()
+            sim.close()
+            del rec, la, lb, gF
+            torch.cuda.empty_cache()
+        print(json.dumps({"probe": "adjoint", "n": n, "steps": K, "sweeps": 3}))
         return
 
     if args.strain_probe:
