@@ -1,6 +1,7 @@
 """Build the HIP library liblbm.so for gfx950 in-tree (hipcc, no JIT).
 
     python -m paper_1704_07559_amd.build        # or  build() from Python
+    python -m paper_1704_07559_amd.build --resources   # registers and occupancy per kernel
 
 Every translation unit under csrc/ is compiled to an object in csrc/_build/ (in parallel)
 and linked into paper_1704_07559_amd/liblbm.so. Packed FP32 instructions are disabled
@@ -92,6 +93,39 @@ def sanitizer_runtime() -> str:
     return r.stdout.strip()
 
 
+def resource_usage() -> list[dict]:
+    """Registers, scratch, LDS and occupancy of every kernel, as the compiler reports them for
+    the device code of each translation unit (-Rpass-analysis=kernel-resource-usage; device
+    compilation only, nothing is written)."""
+    import re
+    fields = {"VGPRs": "vgprs", "AGPRs": "agprs", "ScratchSize [bytes/lane]": "scratch",
+              "Occupancy [waves/SIMD]": "waves_per_simd", "LDS Size [bytes/block]": "lds", "VGPRs Spill": "vgpr_spill"}
+    out = []
+    for src in sorted(CSRC.glob("*.hip")):
+        cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "--cuda-device-only", "-c", str(src), "-o", os.devnull,
+               "-Rpass-analysis=kernel-resource-usage"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src.name}:\n{r.stderr}")
+        cur = None
+        for line in r.stderr.splitlines():
+            m = re.search(r"remark: Function Name: (\S+)", line)
+            if m:
+                cur = {"file": src.name, "kernel": m.group(1)}
+                out.append(cur)
+                continue
+            m = re.search(r"remark:\s+(.+?): (\S+) \[-Rpass-analysis", line)
+            if m and cur is not None and m.group(1) in fields:
+                cur[fields[m.group(1)]] = int(m.group(2)) if m.group(2).isdigit() else m.group(2)
+    return out
+
+
 if __name__ == "__main__":
+    if "--resources" in sys.argv:
+        for k in resource_usage():
+            print(f"{k['file']:24s} vgprs {k.get('vgprs', '?'):>3} agprs {k.get('agprs', '?'):>2} "
+                  f"scratch {k.get('scratch', '?'):>3} lds {k.get('lds', '?'):>6} waves/SIMD "
+                  f"{k.get('waves_per_simd', '?'):>2}  {k['kernel']}")
+        sys.exit(0)
     build(verbose=True)
     sys.exit(0)
