@@ -154,10 +154,10 @@ __device__ __forceinline__ void node_update(float (&g)[Q], unsigned self, const 
 // keeps the pulled values packed; that instance fits 80 VGPRs without spilling and is asked
 // for 6 waves per SIMD (the 16-bit step moves half the bytes per wave, so it needs the extra
 // wave in flight: 4 instead of 5 waves cost it 6.5 %, 6 instead of 5 gained 3.7 %).
-template <typename S, int XMODE, bool CORR>
+template <typename S, int XMODE>
 constexpr bool kPackHalves = Codec<S>::kMixedFma && XMODE != 2;
 template <typename S, int XMODE, bool CORR>
-constexpr int kMinWavesPerEU = (kPackHalves<S, XMODE, CORR> && !CORR) ? 6 : 1;
+constexpr int kMinWavesPerEU = (kPackHalves<S, XMODE> && !CORR) ? 6 : 1;
 
 template <typename S, bool WALLS, int XMODE, bool CORR>
 __global__ __launch_bounds__(kMaxBlock, (kMinWavesPerEU<S, XMODE, CORR>)) void step_kernel(Geo G, ModelF M, ViscF V,
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kMaxBlock, (kMinWavesPerEU<S, XMODE, CORR>)) void s
   float g[Q];
   if constexpr (XMODE == 2) pull_rows_staged<Lat, S, WALLS>(static_cast<const S*>(io.src), G, r, y, g);
   else pull_rows<Lat, S, WALLS, XMODE == 1>(static_cast<const S*>(io.src), G, r, y, g);
-  node_update<CORR, kPackHalves<S, XMODE, CORR>>(g, node_index(G, x, y, z), G, M, V, Fo, io);
+  node_update<CORR, kPackHalves<S, XMODE>>(g, node_index(G, x, y, z), G, M, V, Fo, io);
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
