@@ -93,13 +93,31 @@ def sanitizer_runtime() -> str:
     return r.stdout.strip()
 
 
+_RESOURCE_FIELDS = {"VGPRs": "vgprs", "AGPRs": "agprs", "ScratchSize [bytes/lane]": "scratch",
+                    "Occupancy [waves/SIMD]": "waves_per_simd", "LDS Size [bytes/block]": "lds",
+                    "VGPRs Spill": "vgpr_spill"}
+
+
+def parse_resource_remarks(text: str, file: str) -> list[dict]:
+    """Kernels and their resource figures from the compiler's kernel-resource-usage remarks."""
+    import re
+    out, cur = [], None
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = {"file": file, "kernel": m.group(1)}
+            out.append(cur)
+            continue
+        m = re.search(r"remark:\s+(.+?): (\S+) \[-Rpass-analysis", line)
+        if m and cur is not None and m.group(1) in _RESOURCE_FIELDS:
+            cur[_RESOURCE_FIELDS[m.group(1)]] = int(m.group(2)) if m.group(2).isdigit() else m.group(2)
+    return out
+
+
 def resource_usage() -> list[dict]:
     """Registers, scratch, LDS and occupancy of every kernel, as the compiler reports them for
     the device code of each translation unit (-Rpass-analysis=kernel-resource-usage; device
     compilation only, nothing is written)."""
-    import re
-    fields = {"VGPRs": "vgprs", "AGPRs": "agprs", "ScratchSize [bytes/lane]": "scratch",
-              "Occupancy [waves/SIMD]": "waves_per_simd", "LDS Size [bytes/block]": "lds", "VGPRs Spill": "vgpr_spill"}
     out = []
     for src in sorted(CSRC.glob("*.hip")):
         cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "--cuda-device-only", "-c", str(src), "-o", os.devnull,
@@ -107,16 +125,7 @@ def resource_usage() -> list[dict]:
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src.name}:\n{r.stderr}")
-        cur = None
-        for line in r.stderr.splitlines():
-            m = re.search(r"remark: Function Name: (\S+)", line)
-            if m:
-                cur = {"file": src.name, "kernel": m.group(1)}
-                out.append(cur)
-                continue
-            m = re.search(r"remark:\s+(.+?): (\S+) \[-Rpass-analysis", line)
-            if m and cur is not None and m.group(1) in fields:
-                cur[fields[m.group(1)]] = int(m.group(2)) if m.group(2).isdigit() else m.group(2)
+        out += parse_resource_remarks(r.stderr, src.name)
     return out
 
 

@@ -61,3 +61,21 @@ def test_strain_valu_record_matches_only_its_kernel_sources():
     v = bench.read_valu_strain(bench.kernel_source_sha(bench.STRAIN_SOURCES))
     assert v is None or (v["query_chai"] > v["query_yu"] and v["step_drive_chai"] > v["step_drive_yu"])
     assert bench.read_valu_strain("0" * 16) is None
+
+
+def test_resource_remarks_are_parsed():
+    """The kernel-resource-usage remarks hipcc prints are turned into one record per kernel."""
+    from paper_1704_07559_amd.build import parse_resource_remarks
+    text = "\n".join([
+        "k.hip:1:1: remark: Function Name: _Z1kv [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:1:1: remark:     VGPRs: 80 [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:1:1: remark:     Occupancy [waves/SIMD]: 6 [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:1:1: remark:     Dynamic Stack: False [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:1:1: remark:     LDS Size [bytes/block]: 10240 [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:2:1: remark: Function Name: _Z1jv [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:2:1: remark:     VGPRs: 90 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    ks = parse_resource_remarks(text, "k.hip")
+    assert ks == [{"file": "k.hip", "kernel": "_Z1kv", "vgprs": 80, "scratch": 0, "waves_per_simd": 6, "lds": 10240},
+                  {"file": "k.hip", "kernel": "_Z1jv", "vgprs": 90}]
