@@ -474,6 +474,31 @@ inline Launch node_launch(const Geo& G) {
   return L;
 }
 
+// Occupancy caps. Some of the streaming kernels run faster with fewer blocks per CU than their
+// registers allow (fewer address streams in flight at once per CU). A launch caps them by
+// reserving LDS the kernel does not use: a 256-thread block holding `total` bytes of LDS lets
+// `blocks` of them share a CU (measured on MI355X with blocks that only sleep, 160 KB of LDS
+// per CU: 5 blocks of exactly 32 KB do not fit, 4 of 40 KB do; the values below sit inside the
+// measured ranges). Returns the dynamic LDS to request on top of the kernel's static LDS
+// (0: no cap). Results do not change: the reserved LDS is never touched.
+inline size_t lds_cap_bytes(int blocks, size_t static_lds) {
+  size_t total = 0;
+  switch (blocks) {
+    case 3: total = 47104; break;
+    case 4: total = 36864; break;
+    case 5: total = 28672; break;
+    case 6: total = 23552; break;
+    default: return 0;
+  }
+  return total > static_lds ? total - static_lds : 0;
+}
+
+// LDS of the exchange of x-shifted values (pull_rows_staged, pull_staged) for a lattice.
+template <class L>
+constexpr size_t staged_lds_bytes() {
+  return static_cast<size_t>(XShifted<L>::N) * 256 * sizeof(float);
+}
+
 // Launch arguments of one step.
 struct StepIO {
   const void* src;

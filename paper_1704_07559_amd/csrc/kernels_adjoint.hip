@@ -442,8 +442,11 @@ static hipError_t launch_adjoint_layout(const Geo& G, const ModelF& M, const Vis
   // whole-row blocks exchange the x-shifted adjoint elements through LDS (pull_mode 2)
   const bool stage = pull_mode(G, L.block) == 2;
   if (V.kind == 0) {
+    // constant viscosity, whole 256-node rows: 6 blocks per CU instead of 7 (+2.5 % at 256^3;
+    // 4 blocks lost 4 %; the 128^3 shape and the lagged kernel run as fast uncapped)
+    const size_t lds = (stage && L.block.x == 256) ? lds_cap_bytes(6, staged_lds_bytes<LatRev>()) : 0;
     if (stage)
-      hipLaunchKernelGGL((adjoint_kernel<false, true, IN_ROWS, OUT_ROWS>), L.grid, L.block, 0, st, G, M, V, Fo, rec,
+      hipLaunchKernelGGL((adjoint_kernel<false, true, IN_ROWS, OUT_ROWS>), L.grid, L.block, lds, st, G, M, V, Fo, rec,
                          lam_in, lam_out, grad_force);
     else
       hipLaunchKernelGGL((adjoint_kernel<false, false, IN_ROWS, OUT_ROWS>), L.grid, L.block, 0, st, G, M, V, Fo, rec,

@@ -177,13 +177,24 @@ __global__ __launch_bounds__(kMaxBlock, (kMinWavesPerEU<S, XMODE, CORR>)) void s
 template <typename S, bool CORR>
 static void launch_step_c(bool walls, const Launch& L, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const StepIO& io) {
-  switch (pull_mode(G, L.block) + (walls ? 3 : 0)) {
-    case 0: hipLaunchKernelGGL((step_kernel<S, false, 0, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
-    case 1: hipLaunchKernelGGL((step_kernel<S, false, 1, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
-    case 2: hipLaunchKernelGGL((step_kernel<S, false, 2, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
-    case 3: hipLaunchKernelGGL((step_kernel<S, true, 0, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
-    case 4: hipLaunchKernelGGL((step_kernel<S, true, 1, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
-    default: hipLaunchKernelGGL((step_kernel<S, true, 2, CORR>), L.grid, L.block, 0, st, G, M, V, Fo, io); break;
+  const int mode = pull_mode(G, L.block);
+  // FP32: 4 blocks per CU instead of the 5 its registers allow, in the two shapes where that
+  // was measured faster (whole 256-node rows: +2.2-3.0 % at 256^3; 128 x 2 part rows: +1.8 % at
+  // 384^3); whole 128-node rows (the 128 x 128 x 512 channel) ran as fast uncapped and 4.4 %
+  // slower capped, so other shapes keep their occupancy. The 16-bit steps want more waves,
+  // not fewer.
+  size_t lds = 0;
+  if constexpr (sizeof(S) == 4) {
+    if (mode == 2 && L.block.x == 256 && L.block.y == 1) lds = lds_cap_bytes(4, staged_lds_bytes<Lat>());
+    else if (mode == 0 && L.block.x == 128 && L.block.y == 2) lds = lds_cap_bytes(4, 0);
+  }
+  switch (mode + (walls ? 3 : 0)) {
+    case 0: hipLaunchKernelGGL((step_kernel<S, false, 0, CORR>), L.grid, L.block, lds, st, G, M, V, Fo, io); break;
+    case 1: hipLaunchKernelGGL((step_kernel<S, false, 1, CORR>), L.grid, L.block, lds, st, G, M, V, Fo, io); break;
+    case 2: hipLaunchKernelGGL((step_kernel<S, false, 2, CORR>), L.grid, L.block, lds, st, G, M, V, Fo, io); break;
+    case 3: hipLaunchKernelGGL((step_kernel<S, true, 0, CORR>), L.grid, L.block, lds, st, G, M, V, Fo, io); break;
+    case 4: hipLaunchKernelGGL((step_kernel<S, true, 1, CORR>), L.grid, L.block, lds, st, G, M, V, Fo, io); break;
+    default: hipLaunchKernelGGL((step_kernel<S, true, 2, CORR>), L.grid, L.block, lds, st, G, M, V, Fo, io); break;
   }
 }
 

@@ -23,7 +23,9 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStrea
   if (n4 == 0) return hipSuccess;
   const size_t blocks = (n4 + 255) / 256;
   if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(stream_copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+  // 5 blocks per CU instead of 8: the copy's own best (6.73 against 6.63 TB/s for 1 GiB; 6 blocks
+  // 6.69, 4 blocks 6.38), so that it stays the ceiling the step is compared with
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), lds_cap_bytes(5, 0), st,
                      static_cast<const v4f*>(src), static_cast<v4f*>(dst), n4);
   return hipGetLastError();
 }
