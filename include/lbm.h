@@ -129,7 +129,9 @@ size_t lbm_population_bytes(const lbm_params* p);
  * Create a context over caller-owned device buffers and write the initial state.
  *  f_a, f_b     two distinct population buffers of lbm_population_bytes(p) bytes.
  *  s_nu_field   device float[N]; required for LBM_VISC_SMAGORINSKY and LBM_VISC_POWERLAW
- *               (may be NULL otherwise). Filled with the initial s_nu.
+ *               (may be NULL otherwise). Filled with the initial s_nu. For D2Q9 boxes that
+ *               take two steps per launch (see lbm_step) the context allocates a second
+ *               float[N] for the field between the two launches of a four-step group.
  *  rho_u        device float[4*N]: planes delta_rho, u_x, u_y, u_z (u_z ignored for D2Q9);
  *               NULL = fluid at rest. Initial populations are g^eq(delta_rho, rho0 u)
  *               (the delta-rho form of Eq. edf).
@@ -146,7 +148,11 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
 
 /*
  * Advance nsteps steps of Eq. mrteq (collide with moment-space relaxation, Eq. mrteqvT,
- * then pull streaming), one fused kernel per step.
+ * then pull streaming), one fused kernel per step. D2Q9 on periodic boxes at least 256 nodes
+ * wide, without S_out and without a force-corrected strain, takes its steps in
+ * groups of four as two launches of two steps each (the intermediate level never leaves the
+ * chip; half the HBM traffic); the remaining steps run singly. The result is the same, bit for
+ * bit, as that of nsteps single steps.
  *  S_out        device float[6*N] (D3Q19, D3Q15) / [3*N] (D2Q9) or NULL: receives, at every step,
  *               the strain (formula `strain_kind`) of that step's pre-collision state; after
  *               the call it holds the strain of the state at level n_end - 1.
@@ -162,7 +168,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
  *               solved rate).
  * Only kernel launches are queued on `stream` (no allocation, copy or wait), so calls can be
  * captured into a HIP graph. The context alternates its two population buffers on the host
- * at every step: a captured sequence must hold an even number of steps for each replay to
+ * at every launch, and a call of an even number of steps leaves the state in the buffer it
+ * started from: a captured sequence must hold an even number of steps for each replay to
  * start from the buffer the capture started from, and lbm_step_count counts the captured
  * steps only.
  */

@@ -29,6 +29,7 @@ struct lbm_ctx {
   void* buf[2];
   int cur;          // buffer holding the current internal state
   float* snu;       // lagged s_nu field (variable viscosity) or nullptr
+  float* snu_pair;  // D2Q9 two-step launches with a lagged s_nu: the field between two of them
   double* scratch;  // reduction partials (kReduceBlocks * 8) + result (8)
   long long step;
 };
@@ -235,6 +236,15 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
     (void)hipGetLastError();
     return fail(LBM_ENOMEM, std::string("hipMalloc of the reduction scratch failed: ") + hipGetErrorString(e));
   }
+  if (c->Q == 9 && c->snu && d2q9::pair_supported(c->G, c->F)) {
+    e = hipMalloc(reinterpret_cast<void**>(&c->snu_pair), sizeof(float) * N);
+    if (e != hipSuccess) {
+      (void)hipFree(c->scratch);
+      delete c;
+      (void)hipGetLastError();
+      return fail(LBM_ENOMEM, std::string("hipMalloc of the second s_nu field failed: ") + hipGetErrorString(e));
+    }
+  }
   const hipStream_t s = as_stream(stream);
   switch (c->Q) {
     case 19: e = d3q19::launch_init(p->storage, c->G, c->M, c->buf[0], c->snu, rho_u, grad_u, s); break;
@@ -243,6 +253,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
   }
   if (e != hipSuccess) {
     (void)hipFree(c->scratch);
+    if (c->snu_pair) (void)hipFree(c->snu_pair);
     delete c;
     return hip_fail(e, "lbm_init");
   }
@@ -270,7 +281,23 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
   if (save && !has_adjoint(c)) return fail(LBM_EUNSUPPORTED, "the adjoint record is provided for D3Q19 only");
   const size_t rec_elems = static_cast<size_t>(has_adjoint(c) ? save_planes(c->V) : 0) * c->G.N;
   const hipStream_t s = as_stream(stream);
-  for (int n = 0; n < nsteps; ++n) {
+  int n = 0;
+  if (c->Q == 9 && !S_out && d2q9::pair_supported(c->G, c->F)) {
+    // D2Q9: two steps per launch, two launches at a time, so that the population buffers and
+    // the lagged field end where single steps leave them (s_nu: field -> snu_pair -> field)
+    for (; nsteps - n >= 4; n += 4) {
+      for (int h = 0; h < 2; ++h) {
+        float* from = h == 0 ? c->snu : c->snu_pair;
+        float* to = h == 0 ? c->snu_pair : c->snu;
+        hipError_t e = d2q9::launch_pair(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->buf[1 - c->cur],
+                                         c->snu ? from : nullptr, c->snu ? to : nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "lbm_step");
+        c->cur = 1 - c->cur;
+        c->step += 2;
+      }
+    }
+  }
+  for (; n < nsteps; ++n) {
     StepIO io;
     io.src = c->buf[c->cur];
     io.dst = c->buf[1 - c->cur];
@@ -549,6 +576,7 @@ lbm_status lbm_init_adjoint(lbm_ctx* c, const float* rho_u, const float* lam0, f
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   if (c->scratch) (void)hipFree(c->scratch);
+  if (c->snu_pair) (void)hipFree(c->snu_pair);
   delete c;
 }
 

@@ -418,29 +418,32 @@ __device__ __forceinline__ float viscous_slope(float gamma, const ViscF& V) {
 //   s (c + k |P + s A|) = 1,  c = 3 nu0 + 1/2, k = 3 C_s^2, |S| = sqrt(2 S:S),
 // whose left side increases with s. NC = 6 (3D, xx yy zz xy xz yz) or 3 (2D, xx yy xy);
 // off-diagonal components count twice in S:S. Newton from the root of the P = 0 case,
-// k sqrt(2 A:A) s^2 + c s - 1 = 0; three steps reach FP32 resolution.
+// k sqrt(2 A:A) s^2 + c s - 1 = 0; three steps reach FP32 resolution. Every product that
+// meets a sum is an explicit FMA, so that the rate rounds the same in every kernel (left to
+// the compiler, which product of a sum of two products gets fused depends on the code around).
 template <int NC>
 __device__ __forceinline__ float implicit_smagorinsky(const float (&P)[NC], const float (&A)[NC], float nu0,
                                                      float csmag2) {
   static_assert(NC == 6 || NC == 3, "3D or 2D symmetric tensor");
   constexpr int ndiag = NC == 6 ? 3 : 2;
-  const float c = 3.0f * nu0 + 0.5f, k = 3.0f * csmag2;
-  float PP = 0.f, PA = 0.f, AA = 0.f;
+  const float c = __builtin_fmaf(3.0f, nu0, 0.5f), k = 3.0f * csmag2;
+  float PP = P[0] * P[0], PA = P[0] * A[0], AA = A[0] * A[0];
 #pragma unroll
-  for (int i = 0; i < NC; ++i) {
+  for (int i = 1; i < NC; ++i) {
     const float w = i < ndiag ? 1.0f : 2.0f;
-    PP += w * P[i] * P[i];
-    PA += w * P[i] * A[i];
-    AA += w * A[i] * A[i];
+    PP = __builtin_fmaf(w * P[i], P[i], PP);
+    PA = __builtin_fmaf(w * P[i], A[i], PA);
+    AA = __builtin_fmaf(w * A[i], A[i], AA);
   }
   const float q = k * fast_sqrt(2.0f * AA);
-  float s = 2.0f * fast_rcp(c + fast_sqrt(c * c + 4.0f * q));
+  float s = 2.0f * fast_rcp(c + fast_sqrt(__builtin_fmaf(c, c, 4.0f * q)));
 #pragma unroll
   for (int it = 0; it < 3; ++it) {
-    const float r = fast_sqrt(fmaxf(2.0f * (PP + s * (2.0f * PA + s * AA)), 0.0f));
-    const float dr = r > 0.0f ? 2.0f * (PA + s * AA) * fast_rcp(r) : 0.0f;
-    const float f = s * (c + k * r) - 1.0f;
-    s -= f * fast_rcp(c + k * r + s * k * dr);
+    const float r = fast_sqrt(fmaxf(2.0f * __builtin_fmaf(s, __builtin_fmaf(s, AA, 2.0f * PA), PP), 0.0f));
+    const float dr = r > 0.0f ? 2.0f * __builtin_fmaf(s, AA, PA) * fast_rcp(r) : 0.0f;
+    const float ckr = __builtin_fmaf(k, r, c);
+    const float f = __builtin_fmaf(s, ckr, -1.0f);
+    s = __builtin_fmaf(-f, fast_rcp(__builtin_fmaf(s * k, dr, ckr)), s);
   }
   return s;
 }

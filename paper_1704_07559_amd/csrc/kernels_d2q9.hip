@@ -3,6 +3,12 @@
 // query, canonical gather/scatter and the diagnostics reduction. One thread per node.
 #include <hip/hip_runtime.h>
 
+// Contraction of a product and a sum into an FMA only within one expression of the source
+// (for this file and the headers it includes): left to the code generator, which product of
+// a sum gets fused depends on the code around it, and the two-step kernel below must round
+// every operation as the single step does.
+#pragma clang fp contract(on)
+
 #include "d2q9.h"
 #include "internal.h"
 #include "launch.h"
@@ -30,7 +36,13 @@ __device__ __forceinline__ void rates_with(const ModelF& M, float snu, float (&r
   });
 }
 
-__device__ __forceinline__ float strain_sq(const float (&S)[3]) { return S[0] * S[0] + S[1] * S[1] + 2.0f * S[2] * S[2]; }
+// S:S (the off-diagonal component counts twice) in one fixed order of operations. Written as
+// plain products and sums, the compiler may fuse either product of a sum into an FMA, and
+// which one it picks depends on the code around it, so the same strain could round to two
+// different rates in two kernels; the two-step kernel must round exactly as the single step.
+__device__ __forceinline__ float strain_sq(const float (&S)[3]) {
+  return __builtin_fmaf(S[0], S[0], __builtin_fmaf(S[1], S[1], 2.0f * S[2] * S[2]));
+}
 
 // The force-corrected strain (optional) takes the non-equilibrium part plus half the Guo
 // source, m - m^eq + S_F/2. StrainIn holds the moments the Yu-type formula reads (ns) and,
@@ -114,24 +126,20 @@ __device__ __forceinline__ float query_rate(const Pairs& P, float drho, float jx
   return snu_f ? snu_f[self] : M.s[7];
 }
 
-// XMODE: how a block pulls along x (pull_mode: 0 part rows, 1 whole rows, 2 whole rows with
-// the LDS exchange). CORR: the force-corrected strain (a separate instance, so that the plain
-// step keeps its register budget).
-template <typename S, bool WALLS, int XMODE, bool CORR>
-__global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= G.nx || y >= G.ny) return;
-  const unsigned self = node_index(G, x, y, 0);
-  const Rows<Q, S> r = rows_of<Q, S>(G, x, y, 0);
-  float g[Q];
-  if constexpr (XMODE == 2) pull_rows_staged<Lat, S, WALLS>(static_cast<const S*>(io.src), G, r, y, g);
-  else pull_rows<Lat, S, WALLS, XMODE == 1>(static_cast<const S*>(io.src), G, r, y, g);
+// One node's collision with its strain and viscosity (Eq. mrteq's right side with the rates
+// of Eq. mrteqvT; the strain of Section 5.3, or the Yu-type formula of Section 5.4): g holds
+// the pulled populations on entry and the post-collision ones on return. lagged() gives the
+// node's lagged rate (read only where the lagged coupling needs it), store_lagged(s) keeps
+// the rate a lagged viscosity law derived for the next step. (Fx, Fy): the node's force
+// (load_force). S_out / emit: the optional strain output (emit 1 Yu, 2 Chai). Returns the
+// rate of s_nu's rows this collision used.
+template <bool CORR, class Lagged, class StoreLagged>
+__device__ __forceinline__ float collide(const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo,
+                                         unsigned self, Lagged lagged, StoreLagged store_lagged, float Fx, float Fy,
+                                         float* S_out, int emit, float (&g)[Q]) {
   const Pairs P = make_pairs(g);
   const float drho = delta_rho(P);
   float jx = momentum<0>(P), jy = momentum<1>(P);
-  float Fx, Fy;
-  load_force(Fo, G.N, self, Fx, Fy);
   if (Fo.mode) {
     jx = __builtin_fmaf(0.5f, Fx, jx);
     jy = __builtin_fmaf(0.5f, Fy, jy);
@@ -147,8 +155,8 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   if (V.kind == 3) {
     // implicit coupling: the strain at the rate of this very collision
     snu = implicit_rate(P, drho, jx, jy, si, M, V);
-    if (io.S_out) {
-      if (io.emit == 2) {
+    if (S_out) {
+      if (emit == 2) {
         float r[Q];
         rates_with(M, snu, r);
         strain_chai_in(P, drho, jx, jy, r, si, M.inv_rho0, Sch);
@@ -156,28 +164,26 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
         strain_yu(si.ns, M.s[1], snu, M.inv_rho0, Syu);
       }
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
+      for (int c = 0; c < 3; ++c) stream_store(&S_out[static_cast<size_t>(c) * G.N + self], emit == 2 ? Sch[c] : Syu[c]);
     }
   } else {
     // lagged coupling: the strain of the incoming state with the rates of the previous collision
-    const float snu_prev = io.snu ? io.snu[self] : M.s[7];
-    const bool need_yu = io.emit == 1 || (V.kind != 0 && !V.drive_chai);
-    const bool need_chai = io.emit == 2 || (V.kind != 0 && V.drive_chai);
+    const float snu_prev = lagged();
+    const bool need_yu = emit == 1 || (V.kind != 0 && !V.drive_chai);
+    const bool need_chai = emit == 2 || (V.kind != 0 && V.drive_chai);
     if (need_yu) strain_yu(si.ns, M.s[1], snu_prev, M.inv_rho0, Syu);
     if (need_chai) {
       float r[Q];
       rates_with(M, snu_prev, r);
       strain_chai_in(P, drho, jx, jy, r, si, M.inv_rho0, Sch);
     }
-    if (io.S_out) {
+    if (S_out) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        stream_store(&io.S_out[static_cast<size_t>(c) * G.N + self], io.emit == 2 ? Sch[c] : Syu[c]);
+      for (int c = 0; c < 3; ++c) stream_store(&S_out[static_cast<size_t>(c) * G.N + self], emit == 2 ? Sch[c] : Syu[c]);
     }
     if (V.kind != 0) {
       snu = viscous_rate(V.drive_chai ? strain_sq(Sch) : strain_sq(Syu), V);
-      io.snu[self] = snu;
+      store_lagged(snu);
     }
   }
   float dm[Q];
@@ -199,7 +205,115 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
     });
   }
   add_back_transform(dm, g);
+  return snu;
+}
+
+// XMODE: how a block pulls along x (pull_mode: 0 part rows, 1 whole rows, 2 whole rows with
+// the LDS exchange). CORR: the force-corrected strain (a separate instance, so that the plain
+// step keeps its register budget).
+template <typename S, bool WALLS, int XMODE, bool CORR>
+__global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, StepIO io) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const unsigned self = node_index(G, x, y, 0);
+  const Rows<Q, S> r = rows_of<Q, S>(G, x, y, 0);
+  float g[Q];
+  if constexpr (XMODE == 2) pull_rows_staged<Lat, S, WALLS>(static_cast<const S*>(io.src), G, r, y, g);
+  else pull_rows<Lat, S, WALLS, XMODE == 1>(static_cast<const S*>(io.src), G, r, y, g);
+  float Fx, Fy;
+  load_force(Fo, G.N, self, Fx, Fy);
+  collide<CORR>(
+      G, M, V, Fo, self, [&] { return io.snu ? io.snu[self] : M.s[7]; }, [&](float s) { io.snu[self] = s; }, Fx,
+      Fy, io.S_out, io.emit, g);
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
+}
+
+// Two steps per launch on periodic boxes (no strain output, no force-corrected strain): the
+// result is that of two launches of step_kernel, bit for bit, with half the HBM traffic.
+// A block of 256 lanes owns a strip of kPairStrip columns (lane l at column x0 - 1 + l, the
+// two edge lanes a ring column on either side, wrapped periodically) and kPairRows rows of
+// the result, and walks its rows upwards. At row t it pulls the incoming state from HBM and
+// collides it (level 1, rounded to the storage type as a store would round it); the
+// populations a neighbouring lane pulls at level 2 (c_x != 0) go to an LDS ring of four
+// rows, those the lane itself pulls (c_x = 0) stay in registers. After one barrier it pulls
+// row t - 1 of level 1 (from rows t - 2, t - 1 and t), collides it again and stores it. The
+// ring is four rows deep so that one barrier per row suffices: the slot written at row t + 1
+// is none of the three read at row t. Level 1 is computed for the two ring columns and for
+// one extra row below and above the block's rows, as the neighbouring blocks compute them
+// too: 256 / 254 more columns and (kPairRows + 2) / kPairRows more rows of level-1 work.
+// The lagged rate s_nu cannot be updated in place (a neighbour still reads the old value of
+// a ring node after this block has passed it), so it is read from snu_in and written to
+// snu_out.
+constexpr int kPairStrip = 254;
+// Rows per block: fewer rows mean more level-1 rows computed twice, more rows fewer blocks
+// to overlap one another's barriers and memory waits. Measured at 4096^2: FP32 105.6k MLUPS
+// at 6 rows, 102.9k at 8 and 103.8k at 12; FP16 156.5k, 159.4k and 159.8k.
+template <typename S>
+constexpr int kPairRows = sizeof(S) == 4 ? 6 : 12;
+
+template <typename S>
+__global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* __restrict__ src,
+                                                   S* __restrict__ dst, const float* snu_in, float* snu_out) {
+  using X = XShifted<Lat>;
+  __shared__ float ring[X::N][4][256];
+  const int lane = threadIdx.x;
+  const int x0 = blockIdx.x * kPairStrip;
+  const int xl = x0 - 1 + lane;  // this lane's column, unwrapped
+  // (nx >= 256, so that every lane's column wraps into the box: lanes past the ring column
+  // of a ragged last strip compute level 1 of a column no one reads, and every lane takes
+  // the same path through level 1)
+  const int x = xl < 0 ? xl + G.nx : (xl >= G.nx ? xl - G.nx : xl);
+  const bool kept = lane >= 1 && lane <= kPairStrip && xl < G.nx;  // level 2 owned here
+  const int y0 = blockIdx.y * kPairRows<S>;
+  const int rows = min(kPairRows<S>, G.ny - y0);
+  // level-1 values of the c_x = 0 populations this lane pulls back one and two rows later
+  float prev[Q], prev2[Q], snu_prev = 0.0f;
+  for (int k = 0; k < rows + 2; ++k) {
+    int t = y0 - 1 + k;
+    t = t < 0 ? t + G.ny : (t >= G.ny ? t - G.ny : t);
+    float g[Q];
+    pull_rows<Lat, S, false, false>(src, G, rows_of<Q, S>(G, x, t, 0), t, g);
+    const unsigned self1 = node_index(G, x, t, 0);
+    float Fx, Fy;
+    load_force(Fo, G.N, self1, Fx, Fy);
+    float snu1 = collide<false>(
+        G, M, V, Fo, self1, [&] { return snu_in ? snu_in[self1] : M.s[7]; }, [](float) {}, Fx, Fy, nullptr, 0, g);
+    static_for<Q>([&](auto ii) {
+      constexpr int i = ii;
+      if constexpr (sizeof(S) == 2) g[i] = static_cast<float>(static_cast<S>(g[i]));
+      // opaque: no operation of level 2 may be fused with the last one of level 1
+      asm volatile("" : "+v"(g[i]));
+      if constexpr (Lat::cx(i) != 0) ring[X::slot(i)][k & 3][lane] = g[i];
+    });
+    asm volatile("" : "+v"(snu1));
+    __syncthreads();
+    if (k >= 2 && kept) {
+      const int y = y0 + k - 2;
+      float h[Q];
+      static_for<Q>([&](auto ii) {
+        constexpr int i = ii;
+        constexpr int cx = Lat::cx(i), cy = Lat::cy(i);
+        if constexpr (cx != 0) h[i] = ring[X::slot(i)][(k - 1 - cy) & 3][lane - cx];
+        else if constexpr (cy == 0) h[i] = prev[i];
+        else if constexpr (cy > 0) h[i] = prev2[i];
+        else h[i] = g[i];
+      });
+      const unsigned self = node_index(G, x, y, 0);
+      load_force(Fo, G.N, self, Fx, Fy);
+      collide<false>(
+          G, M, V, Fo, self, [&] { return snu_prev; }, [&](float s) { snu_out[self] = s; }, Fx, Fy, nullptr, 0, h);
+      store_rows<Q>(dst, G, rows_of<Q, S>(G, x, y, 0), h);
+    }
+    static_for<Q>([&](auto ii) {
+      constexpr int i = ii;
+      if constexpr (Lat::cx(i) == 0) {
+        prev2[i] = prev[i];
+        prev[i] = g[i];
+      }
+    });
+    snu_prev = snu1;
+  }
 }
 
 template <typename S>
@@ -356,6 +470,35 @@ hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& 
     case 0: launch_step_t<float>(G.walls != 0, L, st, G, M, V, Fo, io); break;
     case 1: launch_step_t<_Float16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
     case 2: launch_step_t<__bf16>(G.walls != 0, L, st, G, M, V, Fo, io); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename S>
+static void launch_pair_s(unsigned strips, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+                          const ForceF& Fo, const void* src, void* dst, const float* snu_in, float* snu_out) {
+  const dim3 grid(strips, (G.ny + kPairRows<S> - 1) / kPairRows<S>, 1);
+  hipLaunchKernelGGL(pair_kernel<S>, grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst), snu_in,
+                     snu_out);
+}
+
+bool pair_supported(const Geo& G, const ForceF& Fo) {
+  // (narrower boxes leave most lanes of a strip idle; the grid's y extent is at most 65535)
+  return !G.walls && !Fo.strain_corr && G.nz == 1 && G.nx >= 256 && (G.ny + 5) / 6 <= 65535;
+}
+
+hipError_t launch_pair(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const void* src,
+                       void* dst, const float* snu_in, float* snu_out, hipStream_t st) {
+  if (!pair_supported(G, Fo)) return hipErrorInvalidValue;
+  if ((V.kind == 1 || V.kind == 2) != (snu_in != nullptr) || (snu_in != nullptr) != (snu_out != nullptr) ||
+      (snu_in && snu_in == snu_out))
+    return hipErrorInvalidValue;
+  const unsigned strips = (G.nx + kPairStrip - 1) / kPairStrip;
+  switch (storage) {
+    case 0: launch_pair_s<float>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out); break;
+    case 1: launch_pair_s<_Float16>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out); break;
+    case 2: launch_pair_s<__bf16>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -1,0 +1,151 @@
+"""D2Q9 steps taken two per launch (lbm_step on periodic boxes at least 256 wide, in groups of
+four steps) against the same steps taken one launch each, bit for bit: populations, the lagged
+s_nu field and the step counter, in every storage type, viscosity law and force mode, on boxes
+whose width leaves a ragged last strip and whose height leaves a ragged last block of rows;
+then against the FP64 oracle, and replayed from a HIP graph."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import d2q9 as od
+from tests._common import needs_gpu, strain_rel_err, to_np
+from tests.test_gpu_d2q9 import _pop_err, _spec
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+CASES = {
+    "const": dict(),
+    "const_uniform_force": dict(force=np.array([2e-5, -1e-5])),
+    "smag_yu": dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2),
+    "smag_yu_force_field": dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2, force="field"),
+    "powerlaw_chai": dict(visc="powerlaw", drive="chai", K_pl=0.02, n_pl=0.6),
+    "smag_implicit_chai": dict(visc="smagorinsky_implicit", drive="chai", nu0=0.005, c_smag=0.2),
+}
+
+
+def _pair(shape, case, storage, seed):
+    """Two contexts on the same random state: one to be stepped in groups, one singly."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    kw = dict(CASES[case])
+    if isinstance(kw.get("force"), str):
+        kw["force"] = synth.uniform_random_force(shape, seed=seed + 1, amp=1e-4)[:2]
+    _, cp = _spec(shape, **kw)
+    cp.storage = storage
+    g0 = torch.as_tensor(synth.random_state(9, shape, seed=seed, scale=3e-3).astype(np.float32)).cuda()
+    sims = []
+    for _ in range(2):
+        sim = lbm.LBM(cp)
+        sim.set_populations(g0)
+        sims.append(sim)
+    if cp.visc_kind in (capi.LBM_VISC_SMAGORINSKY, capi.LBM_VISC_POWERLAW):
+        # a non-uniform lagged field, as after a first step
+        sims[0].step(1)
+        sims[1].step(1)
+    return sims
+
+
+def _assert_same(a, b, msg):
+    import torch
+    torch.cuda.synchronize()
+    assert torch.equal(a.populations(), b.populations()), msg
+    if a.s_nu is not None:
+        assert torch.equal(a.s_nu, b.s_nu), msg
+    assert a.step_count == b.step_count, msg
+
+
+@pytest.mark.parametrize("shape", [(1, 37, 256), (1, 35, 509), (1, 3, 600), (1, 18, 4096)])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_grouped_steps_equal_single_steps(case, shape):
+    from paper_1704_07559_amd import capi
+    grouped, single = _pair(shape, case, capi.LBM_F32, seed=31)
+    for n in (4, 10):                           # 10 = two groups of four and two single steps
+        grouped.step(n)
+        for _ in range(n):
+            single.step(1)
+        _assert_same(grouped, single, (case, shape, n))
+    grouped.close()
+    single.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("case", ["smag_yu", "smag_yu_force_field", "smag_implicit_chai"])
+def test_grouped_steps_equal_single_steps_16_bit(case, storage):
+    """16-bit storage: the intermediate level is rounded as a store would round it."""
+    from paper_1704_07559_amd import capi
+    st = {"f16": capi.LBM_F16, "bf16": capi.LBM_BF16}[storage]
+    grouped, single = _pair((1, 35, 509), case, st, seed=41)
+    grouped.step(8)
+    for _ in range(8):
+        single.step(1)
+    _assert_same(grouped, single, (case, storage))
+    grouped.close()
+    single.close()
+
+
+def test_grouped_steps_against_oracle():
+    """Twelve steps in three groups from a far-from-equilibrium state with a force field and
+    lagged Smagorinsky: populations and both strains against the FP64 oracle."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape = (1, 33, 300)
+    F = synth.uniform_random_force(shape, seed=52, amp=1e-4)[:2]
+    op, cp = _spec(shape, visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2, force=F)
+    sim = lbm.LBM(cp)
+    g0 = synth.random_state(9, shape, seed=53, scale=3e-3).astype(np.float32).astype(np.float64)
+    sim.set_populations(torch.as_tensor(g0.astype(np.float32)).cuda())
+    ref = od.Simulation(op, g0)
+    for _ in range(3):
+        sim.step(4)
+        ref.step(4)
+        assert _pop_err(to_np(sim.populations()), ref.g) < 1e-5
+        for kind, okind in ((capi.LBM_STRAIN_YU, "yu"), (capi.LBM_STRAIN_CHAI, "chai")):
+            assert strain_rel_err(to_np(sim.strain(kind)), ref.strain(okind)) < 1e-4
+    assert sim.step_count == 12
+    sim.close()
+
+
+def test_grouped_steps_captured_in_a_graph_replay_exactly():
+    """Four steps (two launches of two) captured into a HIP graph: every replay gives the bits
+    of four eager single steps, with eager work between the replays."""
+    import torch
+    from paper_1704_07559_amd import capi
+    cap, eager = _pair((1, 20, 512), "smag_yu", capi.LBM_F32, seed=61)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(graph, stream=st):
+            cap.step(4)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        for _ in range(4):
+            eager.step(1)
+        torch.cuda.synchronize()
+        assert torch.equal(cap.populations(), eager.populations()), rep
+        assert torch.equal(cap.s_nu, eager.s_nu), rep
+        assert cap.reduce()["nonfinite"] == 0
+    cap.close()
+    eager.close()
+
+
+def test_les_4096_squared_grouped_equal_single():
+    """The D2Q9 workload bench.py times (4096^2, FP32, lagged Smagorinsky C_s = 0.1 from the
+    Yu-type strain, tau_nu0 = 0.51, spectrum velocity): 16 steps in four groups against 16
+    single steps, bit for bit."""
+    import torch
+    from paper_1704_07559_amd import lbm
+    m = 4096
+    shape = (1, m, m)
+    u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)[:2]
+    _, cp = _spec(shape, tau=0.51, visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    rho_u = lbm.rho_u_field(np.zeros(shape), u)
+    grouped, single = lbm.LBM(cp, rho_u), lbm.LBM(cp, rho_u)
+    grouped.step(16)
+    for _ in range(16):
+        single.step(1)
+    _assert_same(grouped, single, "4096^2")
+    assert grouped.reduce()["nonfinite"] == 0
+    grouped.close()
+    single.close()
