@@ -256,7 +256,8 @@ template <typename S>
 __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* __restrict__ src,
                                                    S* __restrict__ dst, const float* snu_in, float* snu_out) {
   using X = XShifted<Lat>;
-  __shared__ float ring[X::N][4][256];
+  // (in the storage type: level 1 is rounded to it anyway, and 16-bit rows halve the LDS)
+  __shared__ S ring[X::N][4][256];
   const int lane = threadIdx.x;
   const int x0 = blockIdx.x * kPairStrip;
   const int xl = x0 - 1 + lane;  // this lane's column, unwrapped
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
       if constexpr (sizeof(S) == 2) g[i] = static_cast<float>(static_cast<S>(g[i]));
       // opaque: no operation of level 2 may be fused with the last one of level 1
       asm volatile("" : "+v"(g[i]));
-      if constexpr (Lat::cx(i) != 0) ring[X::slot(i)][k & 3][lane] = g[i];
+      if constexpr (Lat::cx(i) != 0) ring[X::slot(i)][k & 3][lane] = static_cast<S>(g[i]);
     });
     asm volatile("" : "+v"(snu1));
     __syncthreads();
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
       static_for<Q>([&](auto ii) {
         constexpr int i = ii;
         constexpr int cx = Lat::cx(i), cy = Lat::cy(i);
-        if constexpr (cx != 0) h[i] = ring[X::slot(i)][(k - 1 - cy) & 3][lane - cx];
+        if constexpr (cx != 0) h[i] = static_cast<float>(ring[X::slot(i)][(k - 1 - cy) & 3][lane - cx]);
         else if constexpr (cy == 0) h[i] = prev[i];
         else if constexpr (cy > 0) h[i] = prev2[i];
         else h[i] = g[i];
