@@ -601,6 +601,9 @@ def main():
                          "order (counter collection)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--d2q9-probe", choices=("f32", "f16"),
+                    help="only step the 4096^2 D2Q9 LES in that storage: 8 steps two per launch, then 4 "
+                         "one per launch (counter collection)")
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="only run three 6-step adjoint sweeps (lbm_adjoint_steps) on an --n^3 box, constant "
                          "viscosity then lagged Smagorinsky, after the forward steps that record them "
@@ -647,6 +650,21 @@ def main():
         sim.close()
         print(json.dumps({"probe": "slab" if args.slab_probe else args.storage_probe,
                           "steps": args.warmup + args.steps, "nonfinite": d["nonfinite"]}))
+        return
+
+    if args.d2q9_probe:
+        m = 4096
+        w = _workloads()
+        p2 = w.params(w.load("C1"), lattice="D2Q9", grid={"nx": m, "ny": m, "nz": 1})
+        p2.storage = capi.LBM_F16 if args.d2q9_probe == "f16" else capi.LBM_F32
+        u2 = synth.spectrum_velocity((1, m, m), seed=1704, u_rms=0.04)[:2]
+        sim = lbm.LBM(p2, lbm.rho_u_field(np.zeros((1, m, m)), u2))
+        sim.step(8)
+        SingleSteps(sim).step(4)
+        d = sim.reduce(allow_nonfinite=True)
+        sim.close()
+        print(json.dumps({"probe": "d2q9", "storage": args.d2q9_probe, "grouped_launches": 4, "single_launches": 4,
+                          "nonfinite": d["nonfinite"]}))
         return
 
     if args.adjoint_probe:
