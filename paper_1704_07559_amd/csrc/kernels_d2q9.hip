@@ -230,7 +230,8 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
 }
 
 // Two steps per launch on periodic boxes (no strain output, no force-corrected strain): the
-// result is that of two launches of step_kernel, bit for bit, with half the HBM traffic.
+// result is that of two launches of step_kernel, bit for bit, for the algorithmic HBM
+// traffic of one (the rows at block edges are read twice).
 // A block of 256 lanes owns a strip of kPairStrip columns (lane l at column x0 - 1 + l, the
 // two edge lanes a ring column on either side, wrapped periodically) and kPairRows rows of
 // the result, and walks its rows upwards. At row t it pulls the incoming state from HBM and

@@ -59,7 +59,7 @@ def _assert_same(a, b, msg):
 def test_grouped_steps_equal_single_steps(case, shape):
     from paper_1704_07559_amd import capi
     grouped, single = _pair(shape, case, capi.LBM_F32, seed=31)
-    for n in (4, 10):                           # 10 = two groups of four and two single steps
+    for n in (4, 5, 7, 10):                     # groups of four, and 1, 3 or 2 single steps after them
         grouped.step(n)
         for _ in range(n):
             single.step(1)
