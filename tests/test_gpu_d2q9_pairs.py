@@ -130,16 +130,17 @@ def test_grouped_steps_captured_in_a_graph_replay_exactly():
     eager.close()
 
 
-def test_les_4096_squared_grouped_equal_single():
-    """The D2Q9 workload bench.py times (4096^2, FP32, lagged Smagorinsky C_s = 0.1 from the
-    Yu-type strain, tau_nu0 = 0.51, spectrum velocity): 16 steps in four groups against 16
-    single steps, bit for bit."""
-    import torch
-    from paper_1704_07559_amd import lbm
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_les_4096_squared_grouped_equal_single(storage):
+    """The D2Q9 workload bench.py times (4096^2, lagged Smagorinsky C_s = 0.1 from the Yu-type
+    strain, tau_nu0 = 0.51, spectrum velocity), in FP32 and FP16 storage: 16 steps in four
+    groups against 16 single steps, bit for bit."""
+    from paper_1704_07559_amd import capi, lbm
     m = 4096
     shape = (1, m, m)
     u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)[:2]
     _, cp = _spec(shape, tau=0.51, visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    cp.storage = {"f32": capi.LBM_F32, "f16": capi.LBM_F16}[storage]
     rho_u = lbm.rho_u_field(np.zeros(shape), u)
     grouped, single = lbm.LBM(cp, rho_u), lbm.LBM(cp, rho_u)
     grouped.step(16)
