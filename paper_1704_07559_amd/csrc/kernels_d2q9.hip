@@ -236,11 +236,11 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
 // two edge lanes a ring column on either side, wrapped periodically) and kPairRows rows of
 // the result, and walks its rows upwards. At row t it pulls the incoming state from HBM and
 // collides it (level 1, rounded to the storage type as a store would round it); the
-// populations a neighbouring lane pulls at level 2 (c_x != 0) go to an LDS ring of four
-// rows, those the lane itself pulls (c_x = 0) stay in registers. After one barrier it pulls
-// row t - 1 of level 1 (from rows t - 2, t - 1 and t), collides it again and stores it. The
-// ring is four rows deep so that one barrier per row suffices: the slot written at row t + 1
-// is none of the three read at row t. Level 1 is computed for the two ring columns and for
+// populations a neighbouring lane pulls at level 2 (c_x != 0) go to an LDS ring of rows,
+// those the lane itself pulls (c_x = 0) stay in registers. After one barrier it pulls row
+// t - 1 of level 1 (from rows t - 2, t - 1 and t), collides it again and stores it. The ring
+// is deep enough that one barrier per row suffices: the slot written at row t + 1 is none of
+// those read at row t. Level 1 is computed for the two ring columns and for
 // one extra row below and above the block's rows, as the neighbouring blocks compute them
 // too: 256 / 254 more columns and (kPairRows + 2) / kPairRows more rows of level-1 work.
 // The lagged rate s_nu cannot be updated in place (a neighbour still reads the old value of
@@ -253,12 +253,17 @@ constexpr int kPairStrip = 254;
 template <typename S>
 constexpr int kPairRows = sizeof(S) == 4 ? 6 : 12;
 
+// LDS ring rows of the x-shifted populations: one with c_y = -1 is read in the row it was
+// written (2 slots: a fast thread writes the next row while a slow one still reads this one),
+// the others one or two rows later (4 slots); ring_row(i) is population i's first slot.
+constexpr int ring_rows(int i) { return Lat::cx(i) == 0 ? 0 : (Lat::cy(i) < 0 ? 2 : 4); }
+constexpr int ring_row(int i) { return i == 0 ? 0 : ring_row(i - 1) + ring_rows(i - 1); }
+
 template <typename S>
 __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* __restrict__ src,
                                                    S* __restrict__ dst, const float* snu_in, float* snu_out) {
-  using X = XShifted<Lat>;
   // (in the storage type: level 1 is rounded to it anyway, and 16-bit rows halve the LDS)
-  __shared__ S ring[X::N][4][256];
+  __shared__ S ring[ring_row(Q)][256];
   const int lane = threadIdx.x;
   const int x0 = blockIdx.x * kPairStrip;
   const int xl = x0 - 1 + lane;  // this lane's column, unwrapped
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
       if constexpr (sizeof(S) == 2) g[i] = static_cast<float>(static_cast<S>(g[i]));
       // opaque: no operation of level 2 may be fused with the last one of level 1
       asm volatile("" : "+v"(g[i]));
-      if constexpr (Lat::cx(i) != 0) ring[X::slot(i)][k & 3][lane] = static_cast<S>(g[i]);
+      if constexpr (Lat::cx(i) != 0) ring[ring_row(i) + (k & (ring_rows(i) - 1))][lane] = static_cast<S>(g[i]);
     });
     asm volatile("" : "+v"(snu1));
     __syncthreads();
@@ -296,7 +301,8 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
       static_for<Q>([&](auto ii) {
         constexpr int i = ii;
         constexpr int cx = Lat::cx(i), cy = Lat::cy(i);
-        if constexpr (cx != 0) h[i] = static_cast<float>(ring[X::slot(i)][(k - 1 - cy) & 3][lane - cx]);
+        if constexpr (cx != 0)
+          h[i] = static_cast<float>(ring[ring_row(i) + ((k - 1 - cy) & (ring_rows(i) - 1))][lane - cx]);
         else if constexpr (cy == 0) h[i] = prev[i];
         else if constexpr (cy > 0) h[i] = prev2[i];
         else h[i] = g[i];
