@@ -148,8 +148,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
 
 /*
  * Advance nsteps steps of Eq. mrteq (collide with moment-space relaxation, Eq. mrteqvT,
- * then pull streaming), one fused kernel per step. D2Q9 on periodic boxes at least 256 nodes
- * wide, without S_out and without a force-corrected strain, takes its steps in
+ * then pull streaming), one fused kernel per step. D2Q9 on boxes at least 256 nodes wide
+ * (periodic, or with walls in y), without S_out and without a force-corrected strain, takes its steps in
  * groups of four as two launches of two steps each (the intermediate level never leaves the
  * chip; half the HBM traffic); the remaining steps run singly. The result is the same, bit for
  * bit, as that of nsteps single steps.

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
-// Two steps per launch on periodic boxes (no strain output, no force-corrected strain): the
+// Two steps per launch (no strain output, no force-corrected strain): the
 // result is that of two launches of step_kernel, bit for bit, for the algorithmic HBM
 // traffic of one (the rows at block edges are read twice).
 // A block of 256 lanes owns a strip of kPairStrip columns (lane l at column x0 - 1 + l, the
@@ -255,15 +255,22 @@ constexpr int kPairRows = sizeof(S) == 4 ? 6 : 12;
 
 // LDS ring rows of the x-shifted populations: one with c_y = -1 is read in the row it was
 // written (2 slots: a fast thread writes the next row while a slow one still reads this one),
-// the others one or two rows later (4 slots); ring_row(i) is population i's first slot.
-constexpr int ring_rows(int i) { return Lat::cx(i) == 0 ? 0 : (Lat::cy(i) < 0 ? 2 : 4); }
-constexpr int ring_row(int i) { return i == 0 ? 0 : ring_row(i - 1) + ring_rows(i - 1); }
+// the others one or two rows later (4 slots); ring_row(i) is population i's first slot. With
+// walls a population is also read one row later as the opposite of one that bounces back:
+// 4 slots for all.
+template <bool WALLS>
+constexpr int ring_rows(int i) { return Lat::cx(i) == 0 ? 0 : (Lat::cy(i) < 0 && !WALLS ? 2 : 4); }
+template <bool WALLS>
+constexpr int ring_row(int i) { return i == 0 ? 0 : ring_row<WALLS>(i - 1) + ring_rows<WALLS>(i - 1); }
 
-template <typename S>
+// WALLS: halfway bounce-back at y = -1/2 and ny - 1/2 (no wrap in y; level 1 is not computed
+// for the rows beyond the walls, and a population of level 2 that crosses a wall is the
+// opposite one of the node's own level-1 state).
+template <typename S, bool WALLS>
 __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* __restrict__ src,
                                                    S* __restrict__ dst, const float* snu_in, float* snu_out) {
   // (in the storage type: level 1 is rounded to it anyway, and 16-bit rows halve the LDS)
-  __shared__ S ring[ring_row(Q)][256];
+  __shared__ S ring[ring_row<WALLS>(Q)][256];
   const int lane = threadIdx.x;
   const int x0 = blockIdx.x * kPairStrip;
   const int xl = x0 - 1 + lane;  // this lane's column, unwrapped
@@ -276,38 +283,52 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
   const int rows = min(kPairRows<S>, G.ny - y0);
   // level-1 values of the c_x = 0 populations this lane pulls back one and two rows later
   float prev[Q], prev2[Q], snu_prev = 0.0f;
+  constexpr auto slot = [](int i, int row) { return ring_row<WALLS>(i) + (row & (ring_rows<WALLS>(i) - 1)); };
   for (int k = 0; k < rows + 2; ++k) {
     int t = y0 - 1 + k;
-    t = t < 0 ? t + G.ny : (t >= G.ny ? t - G.ny : t);
-    float g[Q];
-    pull_rows<Lat, S, false, false>(src, G, rows_of<Q, S>(G, x, t, 0), t, g);
-    const unsigned self1 = node_index(G, x, t, 0);
-    float Fx, Fy;
-    load_force(Fo, G.N, self1, Fx, Fy);
-    float snu1 = collide<false>(
-        G, M, V, Fo, self1, [&] { return snu_in ? snu_in[self1] : M.s[7]; }, [](float) {}, Fx, Fy, nullptr, 0, g);
-    static_for<Q>([&](auto ii) {
-      constexpr int i = ii;
-      if constexpr (sizeof(S) == 2) g[i] = static_cast<float>(static_cast<S>(g[i]));
-      // opaque: no operation of level 2 may be fused with the last one of level 1
-      asm volatile("" : "+v"(g[i]));
-      if constexpr (Lat::cx(i) != 0) ring[ring_row(i) + (k & (ring_rows(i) - 1))][lane] = static_cast<S>(g[i]);
-    });
-    asm volatile("" : "+v"(snu1));
+    float g[Q], snu1 = 0.0f;
+    if (!WALLS) t = t < 0 ? t + G.ny : (t >= G.ny ? t - G.ny : t);
+    if (!WALLS || (t >= 0 && t < G.ny)) {  // (uniform over the block)
+      pull_rows<Lat, S, WALLS, false>(src, G, rows_of<Q, S>(G, x, t, 0), t, g);
+      const unsigned self1 = node_index(G, x, t, 0);
+      float Fx, Fy;
+      load_force(Fo, G.N, self1, Fx, Fy);
+      snu1 = collide<false>(
+          G, M, V, Fo, self1, [&] { return snu_in ? snu_in[self1] : M.s[7]; }, [](float) {}, Fx, Fy, nullptr, 0, g);
+      static_for<Q>([&](auto ii) {
+        constexpr int i = ii;
+        if constexpr (sizeof(S) == 2) g[i] = static_cast<float>(static_cast<S>(g[i]));
+        // opaque: no operation of level 2 may be fused with the last one of level 1
+        asm volatile("" : "+v"(g[i]));
+        if constexpr (Lat::cx(i) != 0) ring[slot(i, k)][lane] = static_cast<S>(g[i]);
+      });
+      asm volatile("" : "+v"(snu1));
+    } else {
+      static_for<Q>([&](auto ii) { g[ii] = 0.0f; });  // a row beyond a wall: never pulled
+    }
     __syncthreads();
     if (k >= 2 && kept) {
       const int y = y0 + k - 2;
       float h[Q];
       static_for<Q>([&](auto ii) {
         constexpr int i = ii;
-        constexpr int cx = Lat::cx(i), cy = Lat::cy(i);
-        if constexpr (cx != 0)
-          h[i] = static_cast<float>(ring[ring_row(i) + ((k - 1 - cy) & (ring_rows(i) - 1))][lane - cx]);
-        else if constexpr (cy == 0) h[i] = prev[i];
-        else if constexpr (cy > 0) h[i] = prev2[i];
-        else h[i] = g[i];
+        constexpr int cx = Lat::cx(i), cy = Lat::cy(i), o = Lat::opp(i);
+        float v;
+        if constexpr (cx != 0) v = static_cast<float>(ring[slot(i, k - 1 - cy)][lane - cx]);
+        else if constexpr (cy == 0) v = prev[i];
+        else if constexpr (cy > 0) v = prev2[i];
+        else v = g[i];
+        if constexpr (WALLS && cy != 0) {
+          // bounce-back: the opposite population of this node's own level-1 state (row k - 1)
+          float b;
+          if constexpr (Lat::cx(o) != 0) b = static_cast<float>(ring[slot(o, k - 1)][lane]);
+          else b = prev[o];
+          if (crosses_wall<cy>(G, y)) v = b;
+        }
+        h[i] = v;
       });
       const unsigned self = node_index(G, x, y, 0);
+      float Fx, Fy;
       load_force(Fo, G.N, self, Fx, Fy);
       collide<false>(
           G, M, V, Fo, self, [&] { return snu_prev; }, [&](float s) { snu_out[self] = s; }, Fx, Fy, nullptr, 0, h);
@@ -487,13 +508,17 @@ template <typename S>
 static void launch_pair_s(unsigned strips, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const void* src, void* dst, const float* snu_in, float* snu_out) {
   const dim3 grid(strips, (G.ny + kPairRows<S> - 1) / kPairRows<S>, 1);
-  hipLaunchKernelGGL(pair_kernel<S>, grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst), snu_in,
-                     snu_out);
+  if (G.walls)
+    hipLaunchKernelGGL((pair_kernel<S, true>), grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst),
+                       snu_in, snu_out);
+  else
+    hipLaunchKernelGGL((pair_kernel<S, false>), grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst),
+                       snu_in, snu_out);
 }
 
 bool pair_supported(const Geo& G, const ForceF& Fo) {
   // (narrower boxes leave most lanes of a strip idle; the grid's y extent is at most 65535)
-  return !G.walls && !Fo.strain_corr && G.nz == 1 && G.nx >= 256 && (G.ny + 5) / 6 <= 65535;
+  return !Fo.strain_corr && G.nz == 1 && G.nx >= 256 && (G.ny + 5) / 6 <= 65535;
 }
 
 hipError_t launch_pair(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const void* src,

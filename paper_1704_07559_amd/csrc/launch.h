@@ -46,7 +46,7 @@ hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hi
 hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
 hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
                          const float* snu, double* partials, double* out, hipStream_t);
-// Two steps in one launch (periodic boxes at least 256 wide, no force-corrected
+// Two steps in one launch (boxes at least 256 wide, periodic or with walls in y, no force-corrected
 // strain; no strain output): src -> dst, the lagged s_nu field (if any) snu_in -> snu_out
 // (distinct buffers). The result equals two launch_step calls bit for bit.
 bool pair_supported(const Geo&, const ForceF&);

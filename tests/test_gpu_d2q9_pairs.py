@@ -1,8 +1,8 @@
-"""D2Q9 steps taken two per launch (lbm_step on periodic boxes at least 256 wide, in groups of
-four steps) against the same steps taken one launch each, bit for bit: populations, the lagged
-s_nu field and the step counter, in every storage type, viscosity law and force mode, on boxes
-whose width leaves a ragged last strip and whose height leaves a ragged last block of rows;
-then against the FP64 oracle, and replayed from a HIP graph."""
+"""D2Q9 steps taken two per launch (lbm_step on boxes at least 256 wide, periodic or with walls
+in y, in groups of four steps) against the same steps taken one launch each, bit for bit:
+populations, the lagged s_nu field and the step counter, in every storage type, viscosity law
+and force mode, on boxes whose width leaves a ragged last strip and whose height leaves a ragged
+last block of rows; then against the FP64 oracle, and replayed from a HIP graph."""
 import numpy as np
 import pytest
 
@@ -20,6 +20,11 @@ CASES = {
     "smag_yu_force_field": dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2, force="field"),
     "powerlaw_chai": dict(visc="powerlaw", drive="chai", K_pl=0.02, n_pl=0.6),
     "smag_implicit_chai": dict(visc="smagorinsky_implicit", drive="chai", nu0=0.005, c_smag=0.2),
+    "walls_smag_yu_force": dict(visc="smagorinsky", drive="yu", nu0=0.01, c_smag=0.2, walls=True,
+                                force=np.array([2e-5, 0.0])),
+    "walls_powerlaw_chai_force_field": dict(visc="powerlaw", drive="chai", K_pl=0.02, n_pl=0.6, walls=True,
+                                            force="field"),
+    "walls_implicit_yu": dict(visc="smagorinsky_implicit", drive="yu", nu0=0.005, c_smag=0.2, walls=True),
 }
 
 
@@ -69,7 +74,7 @@ def test_grouped_steps_equal_single_steps(case, shape):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-@pytest.mark.parametrize("case", ["smag_yu", "smag_yu_force_field", "smag_implicit_chai"])
+@pytest.mark.parametrize("case", ["smag_yu", "smag_yu_force_field", "smag_implicit_chai", "walls_smag_yu_force"])
 def test_grouped_steps_equal_single_steps_16_bit(case, storage):
     """16-bit storage: the intermediate level is rounded as a store would round it."""
     from paper_1704_07559_amd import capi
@@ -102,6 +107,29 @@ def test_grouped_steps_against_oracle():
         for kind, okind in ((capi.LBM_STRAIN_YU, "yu"), (capi.LBM_STRAIN_CHAI, "chai")):
             assert strain_rel_err(to_np(sim.strain(kind)), ref.strain(okind)) < 1e-4
     assert sim.step_count == 12
+    sim.close()
+
+
+def test_grouped_steps_with_walls_against_oracle():
+    """A channel between halfway bounce-back walls in y, driven by a uniform force, with lagged
+    Smagorinsky from the Chai strain: twelve steps in three groups from a far-from-equilibrium
+    state against the FP64 oracle (the rows next to the walls take their crossing populations
+    from the node's own intermediate state)."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape = (1, 29, 300)
+    op, cp = _spec(shape, visc="smagorinsky", drive="chai", nu0=0.01, c_smag=0.2, walls=True,
+                   force=np.array([1e-5, 0.0]))
+    sim = lbm.LBM(cp)
+    g0 = synth.random_state(9, shape, seed=54, scale=3e-3).astype(np.float32).astype(np.float64)
+    sim.set_populations(torch.as_tensor(g0.astype(np.float32)).cuda())
+    ref = od.Simulation(op, g0)
+    for _ in range(3):
+        sim.step(4)
+        ref.step(4)
+        assert _pop_err(to_np(sim.populations()), ref.g) < 1e-5
+        for kind, okind in ((capi.LBM_STRAIN_YU, "yu"), (capi.LBM_STRAIN_CHAI, "chai")):
+            assert strain_rel_err(to_np(sim.strain(kind)), ref.strain(okind)) < 1e-4
     sim.close()
 
 
