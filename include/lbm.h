@@ -149,13 +149,14 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
 /*
  * Advance nsteps steps of Eq. mrteq (collide with moment-space relaxation, Eq. mrteqvT,
  * then pull streaming), one fused kernel per step. D2Q9 on boxes at least 256 nodes wide
- * (periodic, or with walls in y), without S_out and without a force-corrected strain, takes its steps in
+ * (periodic, or with walls in y) without a force-corrected strain takes its steps in
  * groups of four as two launches of two steps each (the intermediate level never leaves the
  * chip; half the HBM traffic); the remaining steps run singly. The result is the same, bit for
  * bit, as that of nsteps single steps.
- *  S_out        device float[6*N] (D3Q19, D3Q15) / [3*N] (D2Q9) or NULL: receives, at every step,
- *               the strain (formula `strain_kind`) of that step's pre-collision state; after
- *               the call it holds the strain of the state at level n_end - 1.
+ *  S_out        device float[6*N] (D3Q19, D3Q15) / [3*N] (D2Q9) or NULL: receives, at every step
+ *               (at the second step of a launch of two), the strain (formula `strain_kind`) of
+ *               that step's pre-collision state; after the call it holds the strain of the
+ *               state at level n_end - 1.
  *  strain_kind  LBM_STRAIN_YU or LBM_STRAIN_CHAI (ignored when S_out is NULL).
  *  save         device float[nsteps*R*N] or NULL, R = lbm_save_planes(ctx) (D3Q19 only;
  *               LBM_EUNSUPPORTED otherwise):

@@ -282,7 +282,7 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
   const size_t rec_elems = static_cast<size_t>(has_adjoint(c) ? save_planes(c->V) : 0) * c->G.N;
   const hipStream_t s = as_stream(stream);
   int n = 0;
-  if (c->Q == 9 && !S_out && d2q9::pair_supported(c->G, c->F)) {
+  if (c->Q == 9 && d2q9::pair_supported(c->G, c->F)) {
     // D2Q9: two steps per launch, two launches at a time, so that the population buffers and
     // the lagged field end where single steps leave them (s_nu: field -> snu_pair -> field)
     for (; nsteps - n >= 4; n += 4) {
@@ -290,7 +290,8 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
         float* from = h == 0 ? c->snu : c->snu_pair;
         float* to = h == 0 ? c->snu_pair : c->snu;
         hipError_t e = d2q9::launch_pair(c->p.storage, c->G, c->M, c->V, c->F, c->buf[c->cur], c->buf[1 - c->cur],
-                                         c->snu ? from : nullptr, c->snu ? to : nullptr, s);
+                                         c->snu ? from : nullptr, c->snu ? to : nullptr, S_out,
+                                         S_out ? strain_kind : 0, s);
         if (e != hipSuccess) return hip_fail(e, "lbm_step");
         c->cur = 1 - c->cur;
         c->step += 2;

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
-// Two steps per launch (no strain output, no force-corrected strain): the
+// Two steps per launch (no force-corrected strain): the
 // result is that of two launches of step_kernel, bit for bit, for the algorithmic HBM
 // traffic of one (the rows at block edges are read twice).
 // A block of 256 lanes owns a strip of kPairStrip columns (lane l at column x0 - 1 + l, the
@@ -266,9 +266,12 @@ constexpr int ring_row(int i) { return i == 0 ? 0 : ring_row<WALLS>(i - 1) + rin
 // WALLS: halfway bounce-back at y = -1/2 and ny - 1/2 (no wrap in y; level 1 is not computed
 // for the rows beyond the walls, and a population of level 2 that crosses a wall is the
 // opposite one of the node's own level-1 state).
+// S_out / emit: the optional strain output, taken at level 2 only (the strain of the second
+// step's incoming state, which single steps leave in S_out last).
 template <typename S, bool WALLS>
 __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* __restrict__ src,
-                                                   S* __restrict__ dst, const float* snu_in, float* snu_out) {
+                                                   S* __restrict__ dst, const float* snu_in, float* snu_out,
+                                                   float* S_out, int emit) {
   // (in the storage type: level 1 is rounded to it anyway, and 16-bit rows halve the LDS)
   __shared__ S ring[ring_row<WALLS>(Q)][256];
   const int lane = threadIdx.x;
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
       float Fx, Fy;
       load_force(Fo, G.N, self, Fx, Fy);
       collide<false>(
-          G, M, V, Fo, self, [&] { return snu_prev; }, [&](float s) { snu_out[self] = s; }, Fx, Fy, nullptr, 0, h);
+          G, M, V, Fo, self, [&] { return snu_prev; }, [&](float s) { snu_out[self] = s; }, Fx, Fy, S_out, emit, h);
       store_rows<Q>(dst, G, rows_of<Q, S>(G, x, y, 0), h);
     }
     static_for<Q>([&](auto ii) {
@@ -506,14 +509,15 @@ hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& 
 
 template <typename S>
 static void launch_pair_s(unsigned strips, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
-                          const ForceF& Fo, const void* src, void* dst, const float* snu_in, float* snu_out) {
+                          const ForceF& Fo, const void* src, void* dst, const float* snu_in, float* snu_out,
+                          float* S_out, int emit) {
   const dim3 grid(strips, (G.ny + kPairRows<S> - 1) / kPairRows<S>, 1);
   if (G.walls)
     hipLaunchKernelGGL((pair_kernel<S, true>), grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst),
-                       snu_in, snu_out);
+                       snu_in, snu_out, S_out, emit);
   else
     hipLaunchKernelGGL((pair_kernel<S, false>), grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst),
-                       snu_in, snu_out);
+                       snu_in, snu_out, S_out, emit);
 }
 
 bool pair_supported(const Geo& G, const ForceF& Fo) {
@@ -522,16 +526,16 @@ bool pair_supported(const Geo& G, const ForceF& Fo) {
 }
 
 hipError_t launch_pair(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const void* src,
-                       void* dst, const float* snu_in, float* snu_out, hipStream_t st) {
+                       void* dst, const float* snu_in, float* snu_out, float* S_out, int emit, hipStream_t st) {
   if (!pair_supported(G, Fo)) return hipErrorInvalidValue;
   if ((V.kind == 1 || V.kind == 2) != (snu_in != nullptr) || (snu_in != nullptr) != (snu_out != nullptr) ||
       (snu_in && snu_in == snu_out))
     return hipErrorInvalidValue;
   const unsigned strips = (G.nx + kPairStrip - 1) / kPairStrip;
   switch (storage) {
-    case 0: launch_pair_s<float>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out); break;
-    case 1: launch_pair_s<_Float16>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out); break;
-    case 2: launch_pair_s<__bf16>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out); break;
+    case 0: launch_pair_s<float>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out, S_out, emit); break;
+    case 1: launch_pair_s<_Float16>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out, S_out, emit); break;
+    case 2: launch_pair_s<__bf16>(strips, st, G, M, V, Fo, src, dst, snu_in, snu_out, S_out, emit); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -73,6 +73,29 @@ def test_grouped_steps_equal_single_steps(case, shape):
     single.close()
 
 
+@pytest.mark.parametrize("kind", ["yu", "chai"])
+@pytest.mark.parametrize("case", ["smag_yu", "walls_implicit_yu", "smag_yu_force_field"])
+def test_grouped_steps_with_strain_output(case, kind):
+    """With a strain output the launches of two steps write the second step's strain, which is
+    what single steps leave there last: after 4, 5 and 10 steps the output holds the same bits."""
+    import torch
+    from paper_1704_07559_amd import capi
+    shape = (1, 35, 509)
+    sk = {"yu": capi.LBM_STRAIN_YU, "chai": capi.LBM_STRAIN_CHAI}[kind]
+    grouped, single = _pair(shape, case, capi.LBM_F32, seed=71)
+    Sg = torch.full((3,) + shape, float("nan"), device="cuda")
+    Ss = torch.full((3,) + shape, float("nan"), device="cuda")
+    for n in (4, 5, 10):
+        grouped.step(n, S_out=Sg, strain_kind=sk)
+        for _ in range(n):
+            single.step(1, S_out=Ss, strain_kind=sk)
+        _assert_same(grouped, single, (case, kind, n))
+        torch.cuda.synchronize()
+        assert torch.equal(Sg, Ss), (case, kind, n)
+    grouped.close()
+    single.close()
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case", ["smag_yu", "smag_yu_force_field", "smag_implicit_chai", "walls_smag_yu_force"])
 def test_grouped_steps_equal_single_steps_16_bit(case, storage):
