@@ -149,8 +149,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
 /*
  * Advance nsteps steps of Eq. mrteq (collide with moment-space relaxation, Eq. mrteqvT,
  * then pull streaming), one fused kernel per step. D2Q9 on boxes at least 256 nodes wide
- * (periodic, or with walls in y) without a force-corrected strain takes its steps in
- * groups of four as two launches of two steps each (the intermediate level never leaves the
+ * (periodic, or with walls in y) takes its steps in groups of four as two launches of two steps each (the intermediate level never leaves the
  * chip; half the HBM traffic); the remaining steps run singly. The result is the same, bit for
  * bit, as that of nsteps single steps.
  *  S_out        device float[6*N] (D3Q19, D3Q15) / [3*N] (D2Q9) or NULL: receives, at every step

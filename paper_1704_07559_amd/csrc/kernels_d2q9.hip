@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(Geo G, ModelF M, ViscF 
   store_rows<Q>(static_cast<S*>(io.dst), G, r, g);
 }
 
-// Two steps per launch (no force-corrected strain): the
+// Two steps per launch: the
 // result is that of two launches of step_kernel, bit for bit, for the algorithmic HBM
 // traffic of one (the rows at block edges are read twice).
 // A block of 256 lanes owns a strip of kPairStrip columns (lane l at column x0 - 1 + l, the
@@ -265,10 +265,11 @@ constexpr int ring_row(int i) { return i == 0 ? 0 : ring_row<WALLS>(i - 1) + rin
 
 // WALLS: halfway bounce-back at y = -1/2 and ny - 1/2 (no wrap in y; level 1 is not computed
 // for the rows beyond the walls, and a population of level 2 that crosses a wall is the
-// opposite one of the node's own level-1 state).
-// S_out / emit: the optional strain output, taken at level 2 only (the strain of the second
-// step's incoming state, which single steps leave in S_out last).
-template <typename S, bool WALLS>
+// opposite one of the node's own level-1 state). CORR: the force-corrected strain.
+// EMIT: the strain output S_out (emit 1 Yu, 2 Chai), taken at level 2 only (the strain of
+// the second step's incoming state, which single steps leave in S_out last); a template
+// parameter, as its code costs the instances without it 15 VGPRs otherwise.
+template <typename S, bool WALLS, bool CORR, bool EMIT>
 __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, ForceF Fo, const S* __restrict__ src,
                                                    S* __restrict__ dst, const float* snu_in, float* snu_out,
                                                    float* S_out, int emit) {
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
       const unsigned self1 = node_index(G, x, t, 0);
       float Fx, Fy;
       load_force(Fo, G.N, self1, Fx, Fy);
-      snu1 = collide<false>(
+      snu1 = collide<CORR>(
           G, M, V, Fo, self1, [&] { return snu_in ? snu_in[self1] : M.s[7]; }, [](float) {}, Fx, Fy, nullptr, 0, g);
       static_for<Q>([&](auto ii) {
         constexpr int i = ii;
@@ -333,8 +334,9 @@ __global__ __launch_bounds__(256) void pair_kernel(Geo G, ModelF M, ViscF V, For
       const unsigned self = node_index(G, x, y, 0);
       float Fx, Fy;
       load_force(Fo, G.N, self, Fx, Fy);
-      collide<false>(
-          G, M, V, Fo, self, [&] { return snu_prev; }, [&](float s) { snu_out[self] = s; }, Fx, Fy, S_out, emit, h);
+      collide<CORR>(
+          G, M, V, Fo, self, [&] { return snu_prev; }, [&](float s) { snu_out[self] = s; }, Fx, Fy,
+          EMIT ? S_out : nullptr, EMIT ? emit : 0, h);
       store_rows<Q>(dst, G, rows_of<Q, S>(G, x, y, 0), h);
     }
     static_for<Q>([&](auto ii) {
@@ -512,17 +514,29 @@ static void launch_pair_s(unsigned strips, hipStream_t st, const Geo& G, const M
                           const ForceF& Fo, const void* src, void* dst, const float* snu_in, float* snu_out,
                           float* S_out, int emit) {
   const dim3 grid(strips, (G.ny + kPairRows<S> - 1) / kPairRows<S>, 1);
-  if (G.walls)
-    hipLaunchKernelGGL((pair_kernel<S, true>), grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst),
-                       snu_in, snu_out, S_out, emit);
-  else
-    hipLaunchKernelGGL((pair_kernel<S, false>), grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst),
-                       snu_in, snu_out, S_out, emit);
+  const S* in = cb<S>(src);
+  S* out = static_cast<S*>(dst);
+  switch ((G.walls ? 1 : 0) + (Fo.strain_corr ? 2 : 0) + (S_out ? 4 : 0)) {
+#define LBM_PAIR_CASE(c, W, C, E)                                                                                    \
+  case c:                                                                                                              \
+    hipLaunchKernelGGL((pair_kernel<S, W, C, E>), grid, dim3(256), 0, st, G, M, V, Fo, in, out, snu_in, snu_out, S_out, \
+                       emit);                                                                                          \
+    break;
+    LBM_PAIR_CASE(0, false, false, false)
+    LBM_PAIR_CASE(1, true, false, false)
+    LBM_PAIR_CASE(2, false, true, false)
+    LBM_PAIR_CASE(3, true, true, false)
+    LBM_PAIR_CASE(4, false, false, true)
+    LBM_PAIR_CASE(5, true, false, true)
+    LBM_PAIR_CASE(6, false, true, true)
+    LBM_PAIR_CASE(7, true, true, true)
+#undef LBM_PAIR_CASE
+  }
 }
 
 bool pair_supported(const Geo& G, const ForceF& Fo) {
   // (narrower boxes leave most lanes of a strip idle; the grid's y extent is at most 65535)
-  return !Fo.strain_corr && G.nz == 1 && G.nx >= 256 && (G.ny + 5) / 6 <= 65535;
+  return G.nz == 1 && G.nx >= 256 && (G.ny + 5) / 6 <= 65535;
 }
 
 hipError_t launch_pair(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const void* src,

@@ -46,8 +46,7 @@ hipError_t launch_get(int storage, const Geo&, const void* buf, float* canon, hi
 hipError_t launch_set(int storage, const Geo&, void* buf, const float* canon, hipStream_t);
 hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* buf,
                          const float* snu, double* partials, double* out, hipStream_t);
-// Two steps in one launch (boxes at least 256 wide, periodic or with walls in y, no force-corrected
-// strain): src -> dst, the lagged s_nu field (if any) snu_in -> snu_out (distinct buffers);
+// Two steps in one launch (boxes at least 256 wide, periodic or with walls in y): src -> dst, the lagged s_nu field (if any) snu_in -> snu_out (distinct buffers);
 // S_out (or nullptr) receives the strain (emit 1 Yu, 2 Chai) of the second step. The result
 // equals two launch_step calls bit for bit.
 bool pair_supported(const Geo&, const ForceF&);

@@ -25,6 +25,10 @@ CASES = {
     "walls_powerlaw_chai_force_field": dict(visc="powerlaw", drive="chai", K_pl=0.02, n_pl=0.6, walls=True,
                                             force="field"),
     "walls_implicit_yu": dict(visc="smagorinsky_implicit", drive="yu", nu0=0.005, c_smag=0.2, walls=True),
+    "corrected_smag_chai_force_field": dict(visc="smagorinsky", drive="chai", nu0=0.01, c_smag=0.2,
+                                            force="field", strain_force_correction=1),
+    "walls_corrected_implicit_yu_force": dict(visc="smagorinsky_implicit", drive="yu", nu0=0.005, c_smag=0.2,
+                                              walls=True, force=np.array([2e-5, 0.0]), strain_force_correction=1),
 }
 
 
@@ -33,10 +37,12 @@ def _pair(shape, case, storage, seed):
     import torch
     from paper_1704_07559_amd import capi, lbm
     kw = dict(CASES[case])
+    corr = kw.pop("strain_force_correction", 0)
     if isinstance(kw.get("force"), str):
         kw["force"] = synth.uniform_random_force(shape, seed=seed + 1, amp=1e-4)[:2]
     _, cp = _spec(shape, **kw)
     cp.storage = storage
+    cp.strain_force_correction = corr
     g0 = torch.as_tensor(synth.random_state(9, shape, seed=seed, scale=3e-3).astype(np.float32)).cuda()
     sims = []
     for _ in range(2):
@@ -74,7 +80,8 @@ def test_grouped_steps_equal_single_steps(case, shape):
 
 
 @pytest.mark.parametrize("kind", ["yu", "chai"])
-@pytest.mark.parametrize("case", ["smag_yu", "walls_implicit_yu", "smag_yu_force_field"])
+@pytest.mark.parametrize("case", ["smag_yu", "walls_implicit_yu", "smag_yu_force_field",
+                                  "corrected_smag_chai_force_field"])
 def test_grouped_steps_with_strain_output(case, kind):
     """With a strain output the launches of two steps write the second step's strain, which is
     what single steps leave there last: after 4, 5 and 10 steps the output holds the same bits."""
