@@ -236,7 +236,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, fl
     (void)hipGetLastError();
     return fail(LBM_ENOMEM, std::string("hipMalloc of the reduction scratch failed: ") + hipGetErrorString(e));
   }
-  if (c->Q == 9 && c->snu && d2q9::pair_supported(c->G, c->F)) {
+  if (c->Q == 9 && c->snu && d2q9::pair_supported(c->G)) {
     e = hipMalloc(reinterpret_cast<void**>(&c->snu_pair), sizeof(float) * N);
     if (e != hipSuccess) {
       (void)hipFree(c->scratch);
@@ -282,7 +282,7 @@ lbm_status lbm_step(lbm_ctx* c, int nsteps, float* S_out, int strain_kind, float
   const size_t rec_elems = static_cast<size_t>(has_adjoint(c) ? save_planes(c->V) : 0) * c->G.N;
   const hipStream_t s = as_stream(stream);
   int n = 0;
-  if (c->Q == 9 && d2q9::pair_supported(c->G, c->F)) {
+  if (c->Q == 9 && d2q9::pair_supported(c->G)) {
     // D2Q9: two steps per launch, two launches at a time, so that the population buffers and
     // the lagged field end where single steps leave them (s_nu: field -> snu_pair -> field)
     for (; nsteps - n >= 4; n += 4) {

@@ -509,39 +509,41 @@ hipError_t launch_step(int storage, const Geo& G, const ModelF& M, const ViscF& 
   return hipGetLastError();
 }
 
+template <typename S, bool W, bool C, bool E>
+static void launch_pair_k(const dim3& grid, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
+                          const ForceF& Fo, const void* src, void* dst, const float* snu_in, float* snu_out,
+                          float* S_out, int emit) {
+  hipLaunchKernelGGL((pair_kernel<S, W, C, E>), grid, dim3(256), 0, st, G, M, V, Fo, cb<S>(src), static_cast<S*>(dst),
+                     snu_in, snu_out, S_out, emit);
+}
+
 template <typename S>
 static void launch_pair_s(unsigned strips, hipStream_t st, const Geo& G, const ModelF& M, const ViscF& V,
                           const ForceF& Fo, const void* src, void* dst, const float* snu_in, float* snu_out,
                           float* S_out, int emit) {
   const dim3 grid(strips, (G.ny + kPairRows<S> - 1) / kPairRows<S>, 1);
-  const S* in = cb<S>(src);
-  S* out = static_cast<S*>(dst);
+  decltype(&launch_pair_k<S, false, false, false>) k;
   switch ((G.walls ? 1 : 0) + (Fo.strain_corr ? 2 : 0) + (S_out ? 4 : 0)) {
-#define LBM_PAIR_CASE(c, W, C, E)                                                                                    \
-  case c:                                                                                                              \
-    hipLaunchKernelGGL((pair_kernel<S, W, C, E>), grid, dim3(256), 0, st, G, M, V, Fo, in, out, snu_in, snu_out, S_out, \
-                       emit);                                                                                          \
-    break;
-    LBM_PAIR_CASE(0, false, false, false)
-    LBM_PAIR_CASE(1, true, false, false)
-    LBM_PAIR_CASE(2, false, true, false)
-    LBM_PAIR_CASE(3, true, true, false)
-    LBM_PAIR_CASE(4, false, false, true)
-    LBM_PAIR_CASE(5, true, false, true)
-    LBM_PAIR_CASE(6, false, true, true)
-    LBM_PAIR_CASE(7, true, true, true)
-#undef LBM_PAIR_CASE
+    case 0: k = launch_pair_k<S, false, false, false>; break;
+    case 1: k = launch_pair_k<S, true, false, false>; break;
+    case 2: k = launch_pair_k<S, false, true, false>; break;
+    case 3: k = launch_pair_k<S, true, true, false>; break;
+    case 4: k = launch_pair_k<S, false, false, true>; break;
+    case 5: k = launch_pair_k<S, true, false, true>; break;
+    case 6: k = launch_pair_k<S, false, true, true>; break;
+    default: k = launch_pair_k<S, true, true, true>; break;
   }
+  k(grid, st, G, M, V, Fo, src, dst, snu_in, snu_out, S_out, emit);
 }
 
-bool pair_supported(const Geo& G, const ForceF& Fo) {
+bool pair_supported(const Geo& G) {
   // (narrower boxes leave most lanes of a strip idle; the grid's y extent is at most 65535)
   return G.nz == 1 && G.nx >= 256 && (G.ny + 5) / 6 <= 65535;
 }
 
 hipError_t launch_pair(int storage, const Geo& G, const ModelF& M, const ViscF& V, const ForceF& Fo, const void* src,
                        void* dst, const float* snu_in, float* snu_out, float* S_out, int emit, hipStream_t st) {
-  if (!pair_supported(G, Fo)) return hipErrorInvalidValue;
+  if (!pair_supported(G)) return hipErrorInvalidValue;
   if ((V.kind == 1 || V.kind == 2) != (snu_in != nullptr) || (snu_in != nullptr) != (snu_out != nullptr) ||
       (snu_in && snu_in == snu_out))
     return hipErrorInvalidValue;

@@ -49,7 +49,7 @@ hipError_t launch_reduce(int storage, const Geo&, const ModelF&, const ViscF&, c
 // Two steps in one launch (boxes at least 256 wide, periodic or with walls in y): src -> dst, the lagged s_nu field (if any) snu_in -> snu_out (distinct buffers);
 // S_out (or nullptr) receives the strain (emit 1 Yu, 2 Chai) of the second step. The result
 // equals two launch_step calls bit for bit.
-bool pair_supported(const Geo&, const ForceF&);
+bool pair_supported(const Geo&);
 hipError_t launch_pair(int storage, const Geo&, const ModelF&, const ViscF&, const ForceF&, const void* src, void* dst,
                        const float* snu_in, float* snu_out, float* S_out, int emit, hipStream_t);
 }  // namespace d2q9
