@@ -226,8 +226,11 @@ hipError_t launch_reduce(int storage, const Geo& G, const ModelF& M, const ViscF
                          const float* snu, double* partials, double* out, hipStream_t st) {
   unsigned nb = static_cast<unsigned>(G.ny) * G.nz;  // one x-row per block at a time
   if (nb > static_cast<unsigned>(kReduceBlocks)) nb = kReduceBlocks;
+  // FP32: 4 blocks per CU instead of the 5 its registers allow (3.5 % less time per call at
+  // 256^3; 3 blocks 7 % more)
+  const size_t lds = lds_cap_bytes(4, 4 * kReduceVals * sizeof(double));
   switch (storage) {
-    case 0: hipLaunchKernelGGL(reduce_kernel<float>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, cbuf<float>(buf), snu, partials); break;
+    case 0: hipLaunchKernelGGL(reduce_kernel<float>, dim3(nb), dim3(256), lds, st, G, M, V, Fo, cbuf<float>(buf), snu, partials); break;
     case 1: hipLaunchKernelGGL(reduce_kernel<_Float16>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, cbuf<_Float16>(buf), snu, partials); break;
     case 2: hipLaunchKernelGGL(reduce_kernel<__bf16>, dim3(nb), dim3(256), 0, st, G, M, V, Fo, cbuf<__bf16>(buf), snu, partials); break;
     default: return hipErrorInvalidValue;
