@@ -391,7 +391,8 @@ class SingleSteps:
 def other_kernels(torch, np, synth, capi, lbm, u, reps, steps, warmup):
     """The remaining kernels of the path, each against its algorithmic bytes per node: the
     diagnostics reduction (76 + 4 B read) on the 256^3 LES state, and the D2Q9 LES step on
-    4096^2 (9 x 4 x 2 + 8 = 80 B per launch), one launch per step and two steps per launch."""
+    4096^2 (9 x 4 x 2 + 8 = 80 B per launch; 44 with FP16 storage), one launch per step and two
+    steps per launch."""
     out = {}
     n = u.shape[1]
     N = n ** 3
@@ -407,18 +408,20 @@ def other_kernels(torch, np, synth, capi, lbm, u, reps, steps, warmup):
     m = 4096
     u2 = synth.spectrum_velocity((1, m, m), seed=1704, u_rms=0.04)[:2]
     w = _workloads()
-    p2 = w.params(w.load("C1"), lattice="D2Q9", grid={"nx": m, "ny": m, "nz": 1})
-    s2 = lbm.LBM(p2, lbm.rho_u_field(np.zeros((1, m, m)), u2))
-    log(f"D2Q9 {m}^2 LES, one launch per step")
-    single, _ = leg(torch, capi, SingleSteps(s2), m * m, steps, warmup, 80)
-    log(f"D2Q9 {m}^2 LES, two steps per launch")
-    out["d2q9_les_4096sq"], _ = leg(torch, capi, s2, m * m, steps, warmup, 40,
-                                    note="lbm_step takes D2Q9 steps two per launch: 80 B per node "
-                                         "per launch, 40 per step; kernel_ms per step")
-    out["d2q9_les_4096sq"]["one_launch_per_step"] = single
-    out["d2q9_les_4096sq"]["speedup"] = round(out["d2q9_les_4096sq"]["MLUPS"] / single["MLUPS"], 3)
-    s2.close()
-    torch.cuda.empty_cache()
+    for name, storage, bpn in (("d2q9_les_4096sq", capi.LBM_F32, 80), ("d2q9_les_4096sq_f16", capi.LBM_F16, 44)):
+        p2 = w.params(w.load("C1"), lattice="D2Q9", grid={"nx": m, "ny": m, "nz": 1})
+        p2.storage = storage
+        s2 = lbm.LBM(p2, lbm.rho_u_field(np.zeros((1, m, m)), u2))
+        log(f"D2Q9 {m}^2 LES ({name}), one launch per step")
+        single, _ = leg(torch, capi, SingleSteps(s2), m * m, steps, warmup, bpn)
+        log(f"D2Q9 {m}^2 LES ({name}), two steps per launch")
+        out[name], _ = leg(torch, capi, s2, m * m, steps, warmup, bpn // 2,
+                           note=f"lbm_step takes D2Q9 steps two per launch: {bpn} B per node per launch, "
+                                f"{bpn // 2} per step; kernel_ms per step")
+        out[name]["one_launch_per_step"] = single
+        out[name]["speedup"] = round(out[name]["MLUPS"] / single["MLUPS"], 3)
+        s2.close()
+        torch.cuda.empty_cache()
     return out
 
 
