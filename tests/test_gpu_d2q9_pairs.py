@@ -79,6 +79,22 @@ def test_grouped_steps_equal_single_steps(case, shape):
     single.close()
 
 
+@pytest.mark.parametrize("shape,walls", [((1, 1, 256), False), ((1, 2, 300), False), ((1, 2, 300), True),
+                                         ((1, 7, 257), False), ((1, 7, 257), True)])
+def test_grouped_steps_on_degenerate_heights(shape, walls):
+    """Boxes one to a few rows high (rows wrap onto themselves, or the two walls bound two rows)
+    and a strip of one column past the first: grouped steps against single steps, bit for bit."""
+    from paper_1704_07559_amd import capi
+    case = "walls_smag_yu_force" if walls else "smag_yu_force_field"
+    grouped, single = _pair(shape, case, capi.LBM_F32, seed=81)
+    grouped.step(8)
+    for _ in range(8):
+        single.step(1)
+    _assert_same(grouped, single, (shape, walls))
+    grouped.close()
+    single.close()
+
+
 @pytest.mark.parametrize("kind", ["yu", "chai"])
 @pytest.mark.parametrize("case", ["smag_yu", "walls_implicit_yu", "smag_yu_force_field",
                                   "corrected_smag_chai_force_field"])
