@@ -224,3 +224,36 @@ def test_les_4096_squared_grouped_equal_single(storage):
     assert grouped.reduce()["nonfinite"] == 0
     grouped.close()
     single.close()
+
+
+def test_les_4096_squared_grouped_sampled_against_oracle():
+    """The D2Q9 workload in the launch configuration bench.py times (4096^2 FP32, lagged
+    Smagorinsky from the Yu-type strain, two steps per launch): 16 steps in four groups with a
+    strain output, then the populations and the last step's strain at sampled nodes (the box's
+    corners among them) against the FP64 oracle run on each node's 33 x 33 neighbourhood."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    from tests._common import sample_nodes
+    m, K = 4096, 16
+    shape = (1, m, m)
+    u = synth.spectrum_velocity(shape, seed=1704, u_rms=0.04)[:2]
+    op, cp = _spec(shape, tau=0.51, visc="smagorinsky", drive="yu", nu0=(0.51 - 0.5) / 3.0, c_smag=0.1)
+    sim = lbm.LBM(cp, lbm.rho_u_field(np.zeros(shape), u))
+    S = torch.empty((3,) + shape, device="cuda")
+    sim.step(K, S_out=S, strain_kind=capi.LBM_STRAIN_YU)
+    g = sim.populations()
+    worst_g, dS, fr = 0.0, 0.0, 0.0
+    for (_, y, x) in sample_nodes(shape, 24, 19):
+        ix = np.ix_([0], [(y + t) % m for t in range(-K, K + 1)], [(x + t) % m for t in range(-K, K + 1)])
+        up = np.stack([u[c][ix] for c in range(2)])
+        ref = od.Simulation(op, od.init_populations(np.zeros(up.shape[1:]), up, op))
+        for _ in range(K - 1):
+            ref.step(1)
+        S_ref = ref.step(1)[0][:, 0, K, K]
+        got = g[:, 0, y, x].double().cpu().numpy()
+        worst_g = max(worst_g, _pop_err(got[:, None, None, None], ref.g[:, :, K:K + 1, K:K + 1]))
+        dS = max(dS, float(np.abs(S[:, 0, y, x].double().cpu().numpy() - S_ref).max()))
+        fr = max(fr, float(np.sqrt(S_ref[0] ** 2 + S_ref[1] ** 2 + 2 * S_ref[2] ** 2)))
+    sim.close()
+    assert worst_g < 1e-5 and dS / fr < 1e-4, (worst_g, dS / fr)
+
