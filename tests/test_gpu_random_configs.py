@@ -3,8 +3,9 @@ shapes whose row length picks every launch shape (whole rows with masked lanes, 
 through LDS with one to four rows per block, part rows, one node), every viscosity kind and
 drive, walls, no / uniform / field forcing, the force-corrected strain, and tau (D3Q19 also
 rho0). Three steps from a far-from-equilibrium state each; populations 1e-5 and both strain
-formulas 1e-4, as for the fixed cases; with 16-bit storage, the bit-exact rounding property
-of the storage tests; and one D3Q19 adjoint step per configuration against the oracle's."""
+formulas 1e-4, as for the fixed cases; the D2Q9 ones again on boxes at least 256 wide, where
+steps run two per launch; with 16-bit storage, the bit-exact rounding property of the storage
+tests; and one D3Q19 adjoint step per configuration against the oracle's."""
 import numpy as np
 import pytest
 
@@ -90,6 +91,42 @@ def test_random_configuration(lat, k):
         assert strain_rel_err(to_np(S), Sy) < 1e-4, n
         assert strain_rel_err(S_chai, Sc) < 1e-4, n
         assert pop_rel_err(to_np(sim.populations()), ref.g, rho0, od.W) < 1e-5, n
+    sim.close()
+
+
+@pytest.mark.parametrize("k", range(NCONF["d2q9"]))
+def test_random_d2q9_configuration_two_steps_per_launch(k):
+    """The D2Q9 configurations above on boxes at least 256 wide, where lbm_step takes its steps
+    two per launch: eight steps in two groups, with a strain output, against the oracle after
+    each group (populations 1e-5; the output, the last step's strain, and both formulas on the
+    final state 1e-4)."""
+    import torch
+    from paper_1704_07559_amd import capi, lbm
+    shape, kw, force, corrected = _config("d2q9", k)
+    shape = (1, shape[1], 256 + 29 * k)
+    print(f"d2q9 config {k} two per launch: shape {shape} {kw} force={force} corrected={corrected}", flush=True)
+    if force == "uniform":
+        kw["force"] = np.array([2e-5, -1e-5])
+    elif force == "field":
+        kw["force"] = synth.uniform_random_force(shape, seed=700 + k, amp=1e-4)[:2]
+    from oracle import d2q9 as od
+    from tests.test_gpu_d2q9 import _spec
+    op, cp = _spec(shape, **kw)
+    if corrected:
+        op.force_corrected = True
+        cp.strain_force_correction = 1
+    sim = lbm.LBM(cp)
+    g0 = synth.random_state(9, shape, seed=800 + k, scale=3e-3).astype(np.float32).astype(np.float64)
+    sim.set_populations(torch.as_tensor(g0.astype(np.float32)).cuda())
+    ref = od.Simulation(op, g0)
+    S = torch.empty((3,) + shape, device="cuda")
+    for n in range(2):
+        sim.step(4, S_out=S, strain_kind=capi.LBM_STRAIN_CHAI)
+        ref.step(3)
+        Sy, Sc = ref.step(1)
+        assert strain_rel_err(to_np(S), Sc) < 1e-4, n
+        assert pop_rel_err(to_np(sim.populations()), ref.g, 1.0, od.W) < 1e-5, n
+        assert strain_rel_err(to_np(sim.strain(capi.LBM_STRAIN_YU)), ref.strain("yu")) < 1e-4, n
     sim.close()
 
 
