@@ -18,8 +18,9 @@ start from an idle GPU). ``roofline`` prices the step kernel's algorithmic bytes
 the 8 TB/s HBM peak; its kernel time is the device time of all timed launches (HIP events
 on the launch stream around every run of launches between two diagnostics), divided by the
 number of launches. ``extra`` carries the other workloads (FP16/BF16-stored 384^3 runs and
-their FP32 reference, the one-rank slab, implicit Smagorinsky, D3Q15, D2Q9, the power-law
-channel, the adjoint, the Yu/Chai cost comparison of Section 5.2): each is warmed up for at
+their FP32 reference, the one-rank slab, implicit Smagorinsky, D3Q15, D2Q9 in FP32 and FP16
+one and two steps per launch, the power-law channel, the adjoint, the Yu/Chai cost comparison
+of Section 5.2): each is warmed up for at
 least 0.2 s and timed over at least 0.25 s, whatever --steps is. ``cpu_baseline`` times the
 FP64 oracle, single-threaded, on a bounded slab of the same workload and on the full 32^3
 Taylor-Green parity run.
